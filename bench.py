@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the boundary-integral Poisson-Boltzmann hot path on one GPU.
+
+One step = one complete solve of the workload through the C ABI: source
+terms (Eq_Ss), restarted GMRES(10) on the direct-sum product
+(eqdbef1)/(eqdbef2), and the solvation energy (solvation_energy), with the
+inputs already resident on the device.  The headline solver is FP64
+iterative refinement around FP32-pair GMRES cycles; the plain FP64 GMRES
+solver is timed beside it on the same workload.
+
+Printed (one JSON line on stdout):
+  value      Gpair-kernels/s of the mixed solver over the whole step:
+             (FP32 + FP64 products) x N(N-1) ordered pairs / wall time.
+  roofline   the FP32-pair product kernel: 61 algorithmic FLOP per ordered
+             pair x N(N-1) per launch / its average launch time (HIP events
+             around every launch on the solver's stream, timed region only)
+             against the published FP32 vector peak.
+  cpu_baseline  the FP64 CPU oracle's product on the host cores.
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload kirkwood]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "matvec Gpair-kernels/s + solves/s, mixed vs FP64 at <=1e-6 energy rel err"
+FLOP_PER_PAIR = 61          # algorithmic count per ordered pair, FMA = 2
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector peaks
+TOL = 1e-8                  # relative residual of every timed solve
+WORKLOADS = {
+    "kirkwood": "Kirkwood sphere: R=20 A, geodesic nu=32 (N=20480 flat triangles), "
+                "Nc=200 charges uniform in r<=18 A, Q in {-1,+1}; eps1=1, eps2=80, "
+                "kappa=0.1257/A; GMRES(10) to rel. residual 1e-8",
+    "star": "Star-shaped surface R=30 A, nu=64 (N=81920), Nc=2000, Q~N(0,0.5^2); "
+            "eps1=1, eps2=80, kappa=0.1257/A; GMRES(10) to rel. residual 1e-8",
+    "born": "Born ion: sphere R=2 A, nu=8 (N=1280), one +1 charge at the centre; "
+            "eps1=1, eps2=80, kappa=0.1257/A; GMRES(10) to rel. residual 1e-8",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("pair_math.h", "matvec.hip"):
+        with open(os.path.join(ROOT, "paper_1301_5885_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key, workload):
+    """HBM bytes per launch from a committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def golden_energy(workload):
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_reference.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)["energy_kcal_per_mol"]
+
+
+def run_solver(ctx, gabi, torch, u, mode, steps, warmup, pairs):
+    for _ in range(warmup):
+        ctx.solve_dev(u, tol=TOL, mode=mode)
+        ctx.energy_dev(None)
+    torch.cuda.synchronize()
+    for prec in (gabi.FP64, gabi.FP32_PAIR):
+        ctx.kernel_time(prec, reset=True)
+    ctx.set_kernel_timing(True)
+    infos, energies = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(ctx.solve_dev(u, tol=TOL, mode=mode))
+        energies.append(ctx.energy_dev(None))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_kernel_timing(False)
+    kt = {}
+    for prec, key in ((gabi.FP64, "fp64"), (gabi.FP32_PAIR, "fp32")):
+        avg, cnt = ctx.kernel_time(prec, reset=True)
+        kt[key] = (avg, cnt)
+    p64 = sum(i["matvecs_fp64"] for i in infos)
+    p32 = sum(i["matvecs_fp32"] for i in infos)
+    return {
+        "elapsed": elapsed, "infos": infos, "energies": energies,
+        "products_fp64": p64, "products_fp32": p32,
+        "gpairs_per_s": (p64 + p32) * pairs / elapsed / 1e9,
+        "solves_per_s": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "kernel_total_ms": {k: v[0] * v[1] for k, v in kt.items()},
+        "kernel_launches": {k: v[1] for k, v in kt.items()},
+    }
+
+
+def roofline(res, key, n, workload):
+    products = res["products_fp32" if key == "fp32" else "products_fp64"]
+    if products == 0:
+        return None
+    # every launch is timed; launches skipped after an early stop of a cycle
+    # last a few microseconds and are charged to the real products
+    avg_s = res["kernel_total_ms"][key] / products / 1e3
+    flop = FLOP_PER_PAIR * n * (n - 1)
+    achieved = flop / avg_s / 1e12
+    peak = PEAK_TFLOPS[key]
+    t = traffic_from_profiles(f"pair_{key}", workload)
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": t, "kernel": f"pair_kernel<{key}>",
+            "avg_launch_ms": round(avg_s * 1e3, 5),
+            "flop_per_launch": flop}
+
+
+def cpu_baseline(problem, seconds):
+    import numpy as np
+    import oracle
+    el = oracle.mesh_elements(problem.V, problem.F)
+    u = np.random.default_rng(0).normal(size=2 * el.n)
+    pairs = el.n * (el.n - 1)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.matvec(el, u, problem.eps1, problem.eps2, problem.kappa)
+        reps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    elapsed = time.perf_counter() - t0
+    return {"value": round(reps * pairs / elapsed / 1e9, 5), "unit": "Gpair-kernels/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{reps} full FP64 products of the workload (N={el.n}, "
+                      f"{pairs} ordered pairs each), {elapsed:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="kirkwood", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the row-sharded multi-GPU product is a design only)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1301_5885_amd import gabi
+    from paper_1301_5885_amd.synth import config_problem
+
+    p = config_problem(args.workload)
+    n = p.n
+    pairs = n * (n - 1)
+    log(f"[bench] workload {args.workload} N={n} Nc={p.nc}")
+    ctx = gabi.Context(0)
+    ctx.load_problem(p)
+    u = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    E_ref = golden_energy(args.workload)
+
+    results = {}
+    for key, mode in (("mixed", gabi.SOLVE_MIXED_IR), ("fp64", gabi.SOLVE_FP64)):
+        log(f"[bench] timing {key}: {args.warmup} warmup + {args.steps} steps")
+        r = run_solver(ctx, gabi, torch, u, mode, args.steps, args.warmup, pairs)
+        E = r["energies"][-1]
+        r["energy"] = E
+        r["energy_rel_err"] = abs(E / E_ref - 1) if E_ref else None
+        results[key] = r
+        log(f"[bench] {key}: {r['ms_per_step']:.3f} ms/step, "
+            f"{r['gpairs_per_s']:.1f} Gpairs/s, E={E:.8f}, err={r['energy_rel_err']}")
+
+    mixed, fp64 = results["mixed"], results["fp64"]
+    line = {
+        "metric": METRIC,
+        "value": round(mixed["gpairs_per_s"], 3),
+        "unit": "Gpair-kernels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair terms, f64 accumulation/Krylov/residual/energy",
+        "data": "synthetic (seeded geodesic sphere and charges)",
+        "config": {"workload": WORKLOADS[args.workload], "N": n, "Nc": p.nc,
+                   "eps1": p.eps1, "eps2": p.eps2, "kappa": p.kappa,
+                   "restart": 10, "tol": TOL, "solver": "mixed IR (FP32-pair GMRES "
+                   "cycles, FP64 residuals)", "parallelism": "single GPU"},
+        "solves_per_s": round(mixed["solves_per_s"], 3),
+        "energy_rel_err": mixed["energy_rel_err"],
+        "products_per_solve": {"fp32": mixed["products_fp32"] / args.steps,
+                               "fp64": mixed["products_fp64"] / args.steps},
+        "roofline": roofline(mixed, "fp32", n, args.workload),
+        "fp64_solver": {
+            "value": round(fp64["gpairs_per_s"], 3), "unit": "Gpair-kernels/s",
+            "solves_per_s": round(fp64["solves_per_s"], 3),
+            "ms_per_step": round(fp64["ms_per_step"], 4),
+            "energy_rel_err": fp64["energy_rel_err"],
+            "products_per_solve": fp64["products_fp64"] / args.steps,
+            "roofline": roofline(fp64, "fp64", n, args.workload),
+        },
+        "speedup_mixed_over_fp64": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3),
+    }
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline (oracle, ~{args.cpu_seconds:.0f} s)")
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    else:
+        line["cpu_baseline"] = None
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

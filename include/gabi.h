@@ -1,0 +1,195 @@
+/*
+ * gabi.h -- C ABI of libgabi, a direct-sum boundary-integral solver for the
+ * linearized Poisson-Boltzmann equation on MI355X (gfx950).
+ *
+ * Method: W. Geng and F. Jacob, "A GPU-accelerated Direct-sum Boundary
+ * Integral Poisson-Boltzmann Solver", arXiv:1301.5885.
+ *   Problem (Section 1, eqs. (eq1)-(radiation)): a molecule (dielectric eps1,
+ *   point charges q_k at y_k) bounded by a closed surface Gamma, immersed in
+ *   solvent (dielectric eps2, inverse Debye length kappa).
+ *   Unknowns (Section 2.2): u = [phi_1(x_i); d phi_1/d nu(x_i)], i = 0..N-1,
+ *   at the centroids x_i of N flat triangles (centroid collocation).
+ *   Operator (Section 2.2, eqs. (eqdbef1)/(eqdbef2)) with the kernels
+ *   K1..K4 of (Eq_Ls); right-hand side S1, S2 of (Eq_Ss); energy
+ *   (Section 2.3, eq. (solvation_energy)).
+ *
+ * Conventions fixed by this library where the paper is silent or
+ * inconsistent:
+ *   - eps = eps2/eps1 in the kernels and in the diagonal terms (1+eps)/2 and
+ *     (1+1/eps)/2.
+ *   - S1, S2 carry 1/eps1.
+ *   - Charges in units of e, lengths in Angstrom, potentials include the
+ *     1/(4 pi) of G0, energies in kcal/mol (4 pi * 332.0716 kcal A/(mol e^2)).
+ *   - Vectors of length 2N are laid out [phi_0..phi_{N-1}, psi_0..psi_{N-1}].
+ *
+ * Ownership: every input array is copied (or read) during the call; the
+ * caller keeps ownership of all its buffers.  "_dev" entry points take
+ * device pointers (for example from torch tensors) and work on the stream
+ * set with gabi_set_stream; the others take host pointers and synchronize.
+ * A context is not thread-safe: use one context per host thread.
+ *
+ * Errors: every int-returning call returns a gabi_status.  On a negative
+ * status the context is unchanged unless stated otherwise, and
+ * gabi_last_error() describes the failure.
+ */
+#ifndef GABI_H
+#define GABI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gabi_ctx gabi_ctx;
+
+typedef enum {
+    GABI_OK = 0,
+    GABI_NOT_CONVERGED = 1, /* warning: the solution and info are valid      */
+    GABI_EINVAL = -1,       /* bad argument (null pointer, non-finite value) */
+    GABI_ESTATE = -2,       /* surface, charges or parameters not set        */
+    GABI_EMESH = -3,        /* degenerate element data                       */
+    GABI_ENOMEM = -4,       /* device allocation failed                      */
+    GABI_EDEVICE = -5,      /* HIP runtime error                             */
+    GABI_EBUSY = -6         /* resource limit reached (serving)              */
+} gabi_status;
+
+/* Precision of the pair kernels in a product.                              */
+typedef enum {
+    GABI_FP64 = 0,      /* every pair term in FP64                          */
+    GABI_FP32_PAIR = 1  /* pair terms in FP32, row sums accumulated in FP64 */
+} gabi_precision;
+
+/* Solver modes.                                                           */
+typedef enum {
+    GABI_SOLVE_FP64 = 0,     /* restarted GMRES(m) on the FP64 product       */
+    GABI_SOLVE_MIXED_IR = 1  /* FP64 iterative refinement around GMRES(m) on
+                                the FP32-pair product                        */
+} gabi_solve_mode;
+
+typedef struct {
+    int32_t restart;   /* m, Krylov steps per cycle (default 10)              */
+    int32_t maxit;     /* cap on Arnoldi steps over the whole solve (100);
+                          in MIXED_IR: per inner solve                        */
+    double tol;        /* stop when ||b - A u|| / ||b|| <= tol (1e-6), FP64 A */
+    int32_t mode;      /* gabi_solve_mode (GABI_SOLVE_FP64)                   */
+    double inner_tol;  /* MIXED_IR: relative tolerance of each inner solve
+                          (1e-5)                                              */
+    int32_t max_outer; /* MIXED_IR: cap on refinement steps (10)              */
+    int32_t use_graph; /* replay each GMRES cycle as a captured HIP graph (1) */
+} gabi_solve_opts;
+
+typedef struct {
+    int64_t iterations;   /* Arnoldi steps, inner steps included             */
+    int64_t matvecs_fp64; /* FP64 products (explicit residuals included)     */
+    int64_t matvecs_fp32; /* FP32-pair products                               */
+    int64_t restarts;     /* completed GMRES cycles                           */
+    int64_t outer;        /* refinement steps (MIXED_IR), else 0              */
+    double rel_residual;  /* explicit FP64 ||b - A u|| / ||b|| at exit        */
+    int32_t converged;    /* 1 if rel_residual <= tol                         */
+    double seconds;       /* wall time of the call                            */
+} gabi_solve_info;
+
+/* Fill opts with the defaults listed above.                                */
+void gabi_default_opts(gabi_solve_opts *opts);
+
+/* Create a context on HIP device `device` (its null stream until
+ * gabi_set_stream).  *out receives the handle.  GABI_EDEVICE if the device
+ * cannot be used.                                                           */
+int gabi_create(gabi_ctx **out, int device);
+
+/* Free every device buffer of the context.  Null is accepted.              */
+void gabi_destroy(gabi_ctx *ctx);
+
+/* Text of the last error on this context (empty string if none).  The
+ * pointer stays valid until the next call on the context.                  */
+const char *gabi_last_error(const gabi_ctx *ctx);
+
+/* Stream used by all later calls; `stream` is a hipStream_t (0 = null
+ * stream).  The caller keeps ownership of the stream.                       */
+int gabi_set_stream(gabi_ctx *ctx, void *stream);
+
+/* Element data of a triangle mesh (Section 2.2; host utility, no device
+ * work).  xyz: nv x 3 vertex coordinates, row-major.  tri: nf x 3 vertex
+ * indices, counter-clockwise seen from outside.  Outputs (nf each):
+ * centroid = mean of the vertices, unit normal = normalised
+ * (v1-v0)x(v2-v0), area = half its length.  GABI_EMESH for an index out of
+ * range or a zero-area triangle.                                            */
+int gabi_mesh_elements(int64_t nv, const double *xyz, int64_t nf,
+                       const int32_t *tri, double *cx, double *cy, double *cz,
+                       double *nx, double *ny, double *nz, double *area);
+
+/* Set the surface: N elements with centroid (cx,cy,cz), outward unit normal
+ * (nx,ny,nz) and area, host arrays of length n (Section 2.4: the 7N element
+ * arrays).  Rejects n < 4, non-finite values, area <= 0, |normal| off 1 by
+ * more than 1e-6, and two elements with the same centroid (GABI_EMESH).
+ * Discards any previous solution.                                           */
+int gabi_set_surface(gabi_ctx *ctx, int64_t n, const double *cx,
+                     const double *cy, const double *cz, const double *nx,
+                     const double *ny, const double *nz, const double *area);
+
+/* Same, from a triangle mesh (see gabi_mesh_elements).                      */
+int gabi_set_surface_mesh(gabi_ctx *ctx, int64_t nv, const double *xyz,
+                          int64_t nf, const int32_t *tri);
+
+/* Set the point charges: positions (px,py,pz) in Angstrom and charges q in
+ * units of e, host arrays of length nc >= 0 (nc = 0 gives b = 0, u = 0 and
+ * E = 0).  Non-finite values: GABI_EINVAL.  A charge exactly on an element
+ * centroid is rejected with GABI_EINVAL when both surface and charges are
+ * set.                                                                      */
+int gabi_set_charges(gabi_ctx *ctx, int64_t nc, const double *px,
+                     const double *py, const double *pz, const double *q);
+
+/* Dielectric constants eps1 (inside), eps2 (outside) > 0 and inverse Debye
+ * length kappa >= 0 in 1/Angstrom (Section 1, eqs. (eq1)-(eq2)).            */
+int gabi_set_params(gabi_ctx *ctx, double eps1, double eps2, double kappa);
+
+/* Right-hand side b = [S1(x_i); S2(x_i)] / eps1 of (Eq_Ss), 2N values.      */
+int gabi_rhs(gabi_ctx *ctx, double *b);
+int gabi_rhs_dev(gabi_ctx *ctx, double *b_dev);
+
+/* y = A u of (eqdbef1)/(eqdbef2), u and y of length 2N, in the requested
+ * gabi_precision.  The j = i self term is omitted (Section 2.2).            */
+int gabi_matvec(gabi_ctx *ctx, int precision, const double *u, double *y);
+int gabi_matvec_dev(gabi_ctx *ctx, int precision, const double *u_dev,
+                    double *y_dev);
+
+/* Solve A u = b with b from gabi_rhs.  opts may be null (defaults).  x0
+ * (length 2N) is the initial guess, null for zero (Section 2.4).  u receives
+ * the solution (length 2N); info may be null.  Returns GABI_OK,
+ * GABI_NOT_CONVERGED (u and info still valid) or an error.  The solution is
+ * kept on the device for gabi_energy(ctx, NULL, ...).                       */
+int gabi_solve(gabi_ctx *ctx, const gabi_solve_opts *opts, const double *x0,
+               double *u, gabi_solve_info *info);
+int gabi_solve_dev(gabi_ctx *ctx, const gabi_solve_opts *opts,
+                   const double *x0_dev, double *u_dev, gabi_solve_info *info);
+
+/* Electrostatic solvation energy (Section 2.3, eq. (solvation_energy)) in
+ * kcal/mol for the surface values u (length 2N, host for gabi_energy,
+ * device for gabi_energy_dev), or for the last solution if u is null.
+ * Always evaluated in FP64.                                                 */
+int gabi_energy(gabi_ctx *ctx, const double *u, double *e_kcal_per_mol);
+int gabi_energy_dev(gabi_ctx *ctx, const double *u_dev,
+                    double *e_kcal_per_mol);
+
+/* Reaction potential phi_reac(y_k) at every charge (Section 2.3), nc
+ * values written to the host array phi (potential units e/Angstrom with
+ * the 1/(4 pi) of G0), for u as in gabi_energy.                             */
+int gabi_reaction_potential(gabi_ctx *ctx, const double *u, double *phi);
+
+/* Device memory held by the context in bytes.                               */
+int64_t gabi_device_bytes(const gabi_ctx *ctx);
+
+/* Average device duration (milliseconds) of the pair-kernel launches of
+ * products made since the last reset, measured with HIP events around each
+ * launch on the context's stream when timing is enabled; count receives
+ * the number of launches.  Timing adds two event records per product.     */
+int gabi_set_kernel_timing(gabi_ctx *ctx, int enable);
+int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
+                     int64_t *count, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GABI_H */

@@ -81,6 +81,12 @@ def _declare(lib):
     lib.oracle_reaction_potential.argtypes = ops + [_dp, _i64, _dp, _dp, _dp, _dp]
     lib.oracle_energy.argtypes = ops + [_dp, _i64, _dp, _dp, _dp, _dp]
     lib.oracle_energy.restype = C.c_double
+    lib.oracle_num_threads.restype = C.c_int
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().oracle_num_threads())
 
 
 def _p(a):

@@ -35,12 +35,25 @@
  * sequential in j, so results do not depend on the thread count.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORACLE_PI 3.14159265358979323846
 #define ORACLE_COULOMB 332.0716 /* kcal A / (mol e^2) */
+
+/* Threads an OpenMP region of the oracle uses (1 without OpenMP).          */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Element data from a triangle mesh (Section 2.2).                          */

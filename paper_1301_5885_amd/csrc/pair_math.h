@@ -1,0 +1,140 @@
+// Device arithmetic for one target/source pair of the boundary-integral
+// operator (arXiv:1301.5885, Section 2.1 eq. (Eq_Ls), Section 2.2 eqs.
+// (eqdbef1)/(eqdbef2)) on gfx950.
+//
+// Notation for a target x (unit normal nu_x) and a source y:
+//   r = x - y, rho = |r|, tau = kappa rho, E = exp(-tau),
+//   A = E (1 + tau), B = E (3 + 3 tau + tau^2), u_x = r . nu_x.
+// With the 1/(4 pi) of G0/Gk moved into the source weights
+//   s_j = W_j psi_j / (4 pi)          (psi = d phi_1 / d nu)
+//   m_j = W_j phi_j nu_j / (4 pi)     (a vector: folds phi_j and nu_j)
+// the two row sums of the product are
+//   top_i = sum_j (1-E)/rho s_j + (eps A - 1)/rho^3 (r . m_j)
+//         = sum_j W_j [K1 psi_j + K2 phi_j]
+//   bot_i = sum_j -(1 - A/eps) u_x/rho^3 s_j + (A-1)/rho^3 (nu_x . m_j)
+//                 - (B-3) u_x (r . m_j)/rho^5
+//         = sum_j W_j [K3 psi_j + K4 phi_j]
+// since 4 pi K1 = (1-E)/rho, 4 pi K2 = (eps A - 1) u_y/rho^3,
+// 4 pi K3 = -(1 - A/eps) u_x/rho^3 and
+// 4 pi K4 = (A-1) (nu_x . nu_y)/rho^3 - (B-3) u_x u_y/rho^5, u_y = r . nu_y.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gabi {
+
+// ---------------------------------------------------------------------------
+// FP64 e^{-t} for t >= 0 (no FP64 exponential instruction exists on gfx950).
+// Cody-Waite style reduction e^{-t} = 2^k e^{f}, k = rint(-t / ln 2),
+// f = -t - k ln2 in [-ln2/2, ln2/2], one fused multiply-add with ln2 rounded
+// to double (the omitted tail of ln2 contributes |k| * 2.3e-17 absolute to
+// f, below 1e-15 for the t < 745 used here), then the Taylor series of e^f
+// to degree 12 (truncation < 2e-16 relative on |f| <= 0.347), then an
+// exponent add.  t is clamped to 745 so the exponent stays in range; e^{-745}
+// underflows to (sub)normal zero as it should.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_neg_f64(double t) {
+    t = fmin(t, 745.0);
+    const double x = -t;
+    const double kf = __builtin_rint(x * 1.4426950408889634074);  // x / ln2
+    const double f = __builtin_fma(-kf, 0.69314718055994530942, x);
+    double p = 1.0 / 479001600.0;                    // 1/12!
+    p = __builtin_fma(p, f, 1.0 / 39916800.0);       // 1/11!
+    p = __builtin_fma(p, f, 1.0 / 3628800.0);        // 1/10!
+    p = __builtin_fma(p, f, 1.0 / 362880.0);
+    p = __builtin_fma(p, f, 1.0 / 40320.0);
+    p = __builtin_fma(p, f, 1.0 / 5040.0);
+    p = __builtin_fma(p, f, 1.0 / 720.0);
+    p = __builtin_fma(p, f, 1.0 / 120.0);
+    p = __builtin_fma(p, f, 1.0 / 24.0);
+    p = __builtin_fma(p, f, 1.0 / 6.0);
+    p = __builtin_fma(p, f, 0.5);
+    p = __builtin_fma(p, f, 1.0);
+    p = __builtin_fma(p, f, 1.0);
+    return __builtin_ldexp(p, (int)kf);
+}
+
+// FP64 1/sqrt(a) for a > 0: the hardware reciprocal square root estimate
+// refined by one Newton-Raphson step y <- y + y (1 - a y^2) / 2, which
+// squares the estimate's relative error.
+__device__ __forceinline__ double rsqrt_f64(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = a * y;
+    const double e = __builtin_fma(-h, y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 pair: accumulate the contributions of source j to target i.
+//   (tx,ty,tz) target centroid, (tnx,tny,tnz) target normal,
+//   (sx,sy,sz) source centroid, s = W psi/(4 pi), (mx,my,mz) = W phi nu/(4 pi)
+// ---------------------------------------------------------------------------
+struct PairConstF64 {
+    double kappa, eps, inv_eps;
+};
+
+__device__ __forceinline__ void pair_f64(
+    const PairConstF64 &c, double tx, double ty, double tz, double tnx,
+    double tny, double tnz, double sx, double sy, double sz, double s,
+    double mx, double my, double mz, double &top, double &bot) {
+    const double dx = tx - sx, dy = ty - sy, dz = tz - sz;
+    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+    const double rinv = rsqrt_f64(r2);
+    const double rho = r2 * rinv;
+    const double rinv2 = rinv * rinv;
+    const double rinv3 = rinv2 * rinv;
+    const double tau = c.kappa * rho;
+    const double E = exp_neg_f64(tau);
+    const double A = __builtin_fma(E, tau, E);                        // E(1+tau)
+    const double B = E * __builtin_fma(tau, tau + 3.0, 3.0);          // E(3+3tau+tau^2)
+    const double ux = __builtin_fma(dx, tnx, __builtin_fma(dy, tny, dz * tnz));
+    const double w = __builtin_fma(dx, mx, __builtin_fma(dy, my, dz * mz));
+    const double qn = __builtin_fma(tnx, mx, __builtin_fma(tny, my, tnz * mz));
+    // top += (1-E) rinv s + (eps A - 1) rinv3 w
+    const double k1s = __builtin_fma(-E, s, s) * rinv;
+    top += __builtin_fma(__builtin_fma(c.eps, A, -1.0) * rinv3, w, k1s);
+    // bot += (A/eps - 1) ux rinv3 s + (A-1) rinv3 qn - (B-3) rinv2 rinv3 ux w
+    const double uxr3 = ux * rinv3;
+    const double t3 = __builtin_fma(A, c.inv_eps, -1.0) * uxr3 * s;
+    const double t4a = (A - 1.0) * rinv3 * qn;
+    const double t4b = (B - 3.0) * uxr3 * rinv2 * w;
+    bot += (t3 + t4a) - t4b;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 pair (the mixed product): the separation r is formed in FP64 from
+// FP64 centroids and rounded once to FP32, so near pairs keep full FP32
+// relative accuracy; everything after that is FP32 with the hardware
+// exp2 and reciprocal-square-root instructions.
+// ---------------------------------------------------------------------------
+struct PairConstF32 {
+    float kappa, neg_kappa_log2e, eps, inv_eps;
+};
+
+__device__ __forceinline__ void pair_f32(
+    const PairConstF32 &c, double tx, double ty, double tz, float tnx,
+    float tny, float tnz, double sx, double sy, double sz, float s, float mx,
+    float my, float mz, float &top, float &bot) {
+    const float dx = (float)(tx - sx), dy = (float)(ty - sy),
+                dz = (float)(tz - sz);
+    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rho = r2 * rinv;
+    const float rinv2 = rinv * rinv;
+    const float rinv3 = rinv2 * rinv;
+    const float tau = c.kappa * rho;
+    const float E = __builtin_amdgcn_exp2f(rho * c.neg_kappa_log2e);
+    const float A = __builtin_fmaf(E, tau, E);
+    const float B = E * __builtin_fmaf(tau, tau + 3.0f, 3.0f);
+    const float ux = __builtin_fmaf(dx, tnx, __builtin_fmaf(dy, tny, dz * tnz));
+    const float w = __builtin_fmaf(dx, mx, __builtin_fmaf(dy, my, dz * mz));
+    const float qn = __builtin_fmaf(tnx, mx, __builtin_fmaf(tny, my, tnz * mz));
+    const float k1s = __builtin_fmaf(-E, s, s) * rinv;
+    top += __builtin_fmaf(__builtin_fmaf(c.eps, A, -1.0f) * rinv3, w, k1s);
+    const float uxr3 = ux * rinv3;
+    const float t3 = __builtin_fmaf(A, c.inv_eps, -1.0f) * uxr3 * s;
+    const float t4a = (A - 1.0f) * rinv3 * qn;
+    const float t4b = (B - 3.0f) * uxr3 * rinv2 * w;
+    bot += (t3 + t4a) - t4b;
+}
+
+}  // namespace gabi

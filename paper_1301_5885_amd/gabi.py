@@ -1,0 +1,334 @@
+"""Python binding of libgabi (include/gabi.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+and torch tensors to pointers and status codes to exceptions.  If the
+library has not been built the import of ``load()`` fails loudly -- there is
+no fallback.
+
+Host entry points take numpy arrays and return numpy arrays.  ``*_dev``
+entry points take float64 torch tensors on the GPU and run on torch's
+current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgabi.so")
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ESTATE, EMESH, ENOMEM, EDEVICE, EBUSY = -1, -2, -3, -4, -5, -6
+FP64, FP32_PAIR = 0, 1
+SOLVE_FP64, SOLVE_MIXED_IR = 0, 1
+_NAMES = {0: "GABI_OK", 1: "GABI_NOT_CONVERGED", -1: "GABI_EINVAL",
+          -2: "GABI_ESTATE", -3: "GABI_EMESH", -4: "GABI_ENOMEM",
+          -5: "GABI_EDEVICE", -6: "GABI_EBUSY"}
+
+# Every symbol declared in include/gabi.h.
+EXPORTS = (
+    "gabi_default_opts", "gabi_create", "gabi_destroy", "gabi_last_error",
+    "gabi_set_stream", "gabi_mesh_elements", "gabi_set_surface",
+    "gabi_set_surface_mesh", "gabi_set_charges", "gabi_set_params",
+    "gabi_rhs", "gabi_rhs_dev", "gabi_matvec", "gabi_matvec_dev",
+    "gabi_solve", "gabi_solve_dev", "gabi_energy", "gabi_energy_dev",
+    "gabi_reaction_potential", "gabi_device_bytes", "gabi_set_kernel_timing",
+    "gabi_kernel_time",
+)
+
+
+class GabiError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
+                ("mode", C.c_int32), ("inner_tol", C.c_double),
+                ("max_outer", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("matvecs_fp64", C.c_int64),
+                ("matvecs_fp32", C.c_int64), ("restarts", C.c_int64),
+                ("outer", C.c_int64), ("rel_residual", C.c_double),
+                ("converged", C.c_int32), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_vp = C.c_void_p
+_i64 = C.c_int64
+
+
+def load():
+    """Load libgabi.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run __graft_entry__.build() "
+            "(hipcc --offload-arch=gfx950) first")
+    lib = C.CDLL(LIB_PATH)
+    ctx = _vp
+    lib.gabi_default_opts.argtypes = [C.POINTER(SolveOpts)]
+    lib.gabi_default_opts.restype = None
+    lib.gabi_create.argtypes = [C.POINTER(_vp), C.c_int]
+    lib.gabi_destroy.argtypes = [ctx]
+    lib.gabi_destroy.restype = None
+    lib.gabi_last_error.argtypes = [ctx]
+    lib.gabi_last_error.restype = C.c_char_p
+    lib.gabi_set_stream.argtypes = [ctx, _vp]
+    lib.gabi_mesh_elements.argtypes = [_i64, _dp, _i64, C.POINTER(C.c_int32)] + [_dp] * 7
+    lib.gabi_set_surface.argtypes = [ctx, _i64] + [_dp] * 7
+    lib.gabi_set_surface_mesh.argtypes = [ctx, _i64, _dp, _i64, C.POINTER(C.c_int32)]
+    lib.gabi_set_charges.argtypes = [ctx, _i64] + [_dp] * 4
+    lib.gabi_set_params.argtypes = [ctx, C.c_double, C.c_double, C.c_double]
+    lib.gabi_rhs.argtypes = [ctx, _dp]
+    lib.gabi_rhs_dev.argtypes = [ctx, _vp]
+    lib.gabi_matvec.argtypes = [ctx, C.c_int, _dp, _dp]
+    lib.gabi_matvec_dev.argtypes = [ctx, C.c_int, _vp, _vp]
+    lib.gabi_solve.argtypes = [ctx, C.POINTER(SolveOpts), _dp, _dp, C.POINTER(SolveInfo)]
+    lib.gabi_solve_dev.argtypes = [ctx, C.POINTER(SolveOpts), _vp, _vp, C.POINTER(SolveInfo)]
+    lib.gabi_energy.argtypes = [ctx, _dp, _dp]
+    lib.gabi_energy_dev.argtypes = [ctx, _vp, _dp]
+    lib.gabi_reaction_potential.argtypes = [ctx, _dp, _dp]
+    lib.gabi_device_bytes.argtypes = [ctx]
+    lib.gabi_device_bytes.restype = C.c_int64
+    lib.gabi_set_kernel_timing.argtypes = [ctx, C.c_int]
+    lib.gabi_kernel_time.argtypes = [ctx, C.c_int, _dp, C.POINTER(C.c_int64), C.c_int]
+    for name in EXPORTS:
+        if name not in ("gabi_default_opts", "gabi_destroy", "gabi_last_error",
+                        "gabi_device_bytes"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def mesh_elements(V, F):
+    """Element data of a mesh computed by the library (host utility)."""
+    lib = load()
+    V = _f64(V).reshape(-1, 3)
+    F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
+    n = F.shape[0]
+    out = [np.empty(n) for _ in range(7)]
+    rc = lib.gabi_mesh_elements(V.shape[0], _p(V), n,
+                                F.ctypes.data_as(C.POINTER(C.c_int32)),
+                                *[_p(a) for a in out])
+    if rc != OK:
+        raise GabiError(rc, "gabi_mesh_elements")
+    keys = ("cx", "cy", "cz", "nx", "ny", "nz", "area")
+    return dict(zip(keys, out))
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load().gabi_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solve option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _torch_ptr(t, numel=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Problem:
+    """Host-side description handed to a context in one call."""
+    V: np.ndarray
+    F: np.ndarray
+    pos: np.ndarray
+    q: np.ndarray
+    eps1: float = 1.0
+    eps2: float = 80.0
+    kappa: float = 0.1257
+
+
+class Context:
+    """One libgabi context on one device (not thread-safe)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        h = _vp()
+        rc = self._lib.gabi_create(C.byref(h), int(device))
+        if rc != OK:
+            raise GabiError(rc, f"gabi_create(device={device})")
+        self._h = h
+        self.n = 0
+        self.nc = 0
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gabi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc, what, allow_warning=False):
+        if rc == OK or (allow_warning and rc == NOT_CONVERGED):
+            return rc
+        msg = self._lib.gabi_last_error(self._h).decode()
+        raise GabiError(rc, f"{what}: {msg}")
+
+    # -- configuration
+    def set_stream(self, stream=None):
+        """Use a hipStream_t handle (int), a torch stream, or torch's current."""
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        handle = getattr(stream, "cuda_stream", stream)
+        self._check(self._lib.gabi_set_stream(self._h, C.c_void_p(int(handle))),
+                    "gabi_set_stream")
+
+    def set_surface(self, centroids, normals, area):
+        c = _f64(centroids).reshape(-1, 3)
+        nrm = _f64(normals).reshape(-1, 3)
+        a = _f64(area)
+        cols = [np.ascontiguousarray(c[:, k]) for k in range(3)] + \
+               [np.ascontiguousarray(nrm[:, k]) for k in range(3)] + [a]
+        self._check(self._lib.gabi_set_surface(self._h, c.shape[0], *[_p(x) for x in cols]),
+                    "gabi_set_surface")
+        self.n = c.shape[0]
+
+    def set_surface_mesh(self, V, F):
+        V = _f64(V).reshape(-1, 3)
+        F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
+        self._check(self._lib.gabi_set_surface_mesh(
+            self._h, V.shape[0], _p(V), F.shape[0],
+            F.ctypes.data_as(C.POINTER(C.c_int32))), "gabi_set_surface_mesh")
+        self.n = F.shape[0]
+
+    def set_charges(self, pos, q):
+        pos = _f64(pos).reshape(-1, 3)
+        q = _f64(q)
+        cols = [np.ascontiguousarray(pos[:, k]) for k in range(3)] + [q]
+        self._check(self._lib.gabi_set_charges(self._h, q.shape[0], *[_p(x) for x in cols]),
+                    "gabi_set_charges")
+        self.nc = q.shape[0]
+
+    def set_params(self, eps1=1.0, eps2=80.0, kappa=0.1257):
+        self._check(self._lib.gabi_set_params(self._h, eps1, eps2, kappa), "gabi_set_params")
+
+    def load_problem(self, p):
+        self.set_surface_mesh(p.V, p.F)
+        self.set_charges(p.pos, p.q)
+        self.set_params(p.eps1, p.eps2, p.kappa)
+
+    # -- host entry points
+    def rhs(self):
+        b = np.empty(2 * self.n)
+        self._check(self._lib.gabi_rhs(self._h, _p(b)), "gabi_rhs")
+        return b
+
+    def matvec(self, u, precision=FP64):
+        u = _f64(u)
+        if u.shape != (2 * self.n,):
+            raise ValueError("u must have length 2N")
+        y = np.empty(2 * self.n)
+        self._check(self._lib.gabi_matvec(self._h, int(precision), _p(u), _p(y)),
+                    "gabi_matvec")
+        return y
+
+    def solve(self, x0=None, **opts):
+        o = default_opts(**opts)
+        info = SolveInfo()
+        u = np.empty(2 * self.n)
+        x0a = None if x0 is None else _f64(x0)
+        rc = self._lib.gabi_solve(self._h, C.byref(o), _p(x0a), _p(u), C.byref(info))
+        self._check(rc, "gabi_solve", allow_warning=True)
+        return u, info.as_dict()
+
+    def energy(self, u=None):
+        e = C.c_double()
+        ua = None if u is None else _f64(u)
+        self._check(self._lib.gabi_energy(self._h, _p(ua), C.byref(e)), "gabi_energy")
+        return e.value
+
+    def reaction_potential(self, u=None):
+        phi = np.empty(self.nc)
+        ua = None if u is None else _f64(u)
+        self._check(self._lib.gabi_reaction_potential(self._h, _p(ua), _p(phi)),
+                    "gabi_reaction_potential")
+        return phi
+
+    # -- device entry points (torch tensors, current stream)
+    def rhs_dev(self, b):
+        self.set_stream()
+        self._check(self._lib.gabi_rhs_dev(self._h, _torch_ptr(b, 2 * self.n, "b")),
+                    "gabi_rhs_dev")
+
+    def matvec_dev(self, u, y, precision=FP64):
+        self.set_stream()
+        self._check(self._lib.gabi_matvec_dev(
+            self._h, int(precision), _torch_ptr(u, 2 * self.n, "u"),
+            _torch_ptr(y, 2 * self.n, "y")), "gabi_matvec_dev")
+
+    def solve_dev(self, u, x0=None, **opts):
+        self.set_stream()
+        o = default_opts(**opts)
+        info = SolveInfo()
+        x0p = None if x0 is None else _torch_ptr(x0, 2 * self.n, "x0")
+        rc = self._lib.gabi_solve_dev(self._h, C.byref(o), x0p,
+                                      _torch_ptr(u, 2 * self.n, "u"), C.byref(info))
+        self._check(rc, "gabi_solve_dev", allow_warning=True)
+        return info.as_dict()
+
+    def energy_dev(self, u=None):
+        self.set_stream()
+        e = C.c_double()
+        up = None if u is None else _torch_ptr(u, 2 * self.n, "u")
+        self._check(self._lib.gabi_energy_dev(self._h, up, C.byref(e)), "gabi_energy_dev")
+        return e.value
+
+    # -- accounting and timing
+    def device_bytes(self):
+        return int(self._lib.gabi_device_bytes(self._h))
+
+    def set_kernel_timing(self, enable=True):
+        self._check(self._lib.gabi_set_kernel_timing(self._h, int(bool(enable))),
+                    "gabi_set_kernel_timing")
+
+    def kernel_time(self, precision=FP64, reset=False):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        self._check(self._lib.gabi_kernel_time(self._h, int(precision), C.byref(ms),
+                                               C.byref(cnt), int(bool(reset))),
+                    "gabi_kernel_time")
+        return ms.value, cnt.value

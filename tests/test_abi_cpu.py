@@ -1,0 +1,84 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/gabi.h, and its host-only utilities agree with
+the oracle."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_5885_amd import gabi
+from paper_1301_5885_amd.synth import icosphere, star_surface
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gabi.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gabi_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_exports():
+    assert declared_functions() == sorted(gabi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gabi.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", gabi.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (gabi_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_library_is_gfx950():
+    """The library built here embeds a gfx950 code object (bundle id)."""
+    blob = open(gabi.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+
+
+def test_default_opts():
+    o = gabi.default_opts()
+    assert (o.restart, o.maxit, o.tol, o.mode) == (10, 100, 1e-6, gabi.SOLVE_FP64)
+
+
+@pytest.mark.parametrize("kind", ["sphere", "star"])
+def test_mesh_elements_match_oracle(kind):
+    if kind == "sphere":
+        V, F = icosphere(6, 3.0)
+    else:
+        V, F, _ = star_surface(6, 10.0, np.random.default_rng(1))
+    got = gabi.mesh_elements(V, F)
+    ref = oracle.mesh_elements(V, F)
+    for k in ("cx", "cy", "cz", "nx", "ny", "nz", "area"):
+        assert np.allclose(got[k], getattr(ref, k), rtol=1e-15, atol=1e-15), k
+
+
+def test_mesh_elements_rejects_bad_meshes():
+    V, F = icosphere(2, 1.0)
+    bad = F.copy()
+    bad[3, 1] = len(V)          # index out of range
+    with pytest.raises(gabi.GabiError) as e:
+        gabi.mesh_elements(V, bad)
+    assert e.value.code == gabi.EMESH
+    deg = F.copy()
+    deg[0, 2] = deg[0, 1]       # zero-area triangle
+    with pytest.raises(gabi.GabiError) as e:
+        gabi.mesh_elements(V, deg)
+    assert e.value.code == gabi.EMESH
+
+
+def test_create_without_device_fails_cleanly():
+    """With no GPU visible, gabi_create reports GABI_EDEVICE (no crash, no
+    fallback); with a GPU it succeeds."""
+    try:
+        ctx = gabi.Context(0)
+    except gabi.GabiError as e:
+        assert e.code == gabi.EDEVICE
+    else:
+        ctx.close()
