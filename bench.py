@@ -158,6 +158,9 @@ def main():
     ap.add_argument("--workload", default="kirkwood", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="before timing, run one device copy of this many MiB "
+                         "(a kernel of known traffic for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
@@ -173,6 +176,13 @@ def main():
     n = p.n
     pairs = n * (n - 1)
     log(f"[bench] workload {args.workload} N={n} Nc={p.nc}")
+    if args.copy_mb:
+        a = torch.ones(args.copy_mb * 131072, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {args.copy_mb} MiB read + written")
+        del a, b
     ctx = gabi.Context(0)
     ctx.load_problem(p)
     u = torch.empty(2 * n, dtype=torch.float64, device="cuda")
