@@ -1,7 +1,10 @@
-// C ABI of libgabi (declared in include/gabi.h): contexts, validation of the
-// element and charge data, device buffers, and the host/device entry points
-// around the kernels.
+// C ABI of libgabi for a single molecule (declared in include/gabi.h):
+// contexts, validation of element and charge data, and the host/device
+// entry points.  A context owns one slot (the molecule's device buffers) and
+// runs it as a batch of one through the same kernels the batched solver and
+// the server use.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -19,29 +22,6 @@ int fail(gabi_ctx *ctx, int code, const std::string &msg) {
 int hip_fail(gabi_ctx *ctx, hipError_t e, const char *what) {
     return fail(ctx, e == hipErrorOutOfMemory ? GABI_ENOMEM : GABI_EDEVICE,
                 std::string(what) + ": " + hipGetErrorString(e));
-}
-
-int dev_alloc(gabi_ctx *ctx, void **p, size_t bytes) {
-    *p = nullptr;
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(ctx, GABI_ENOMEM,
-                    "device allocation of " + std::to_string(bytes) + " bytes failed: " +
-                        hipGetErrorString(e));
-    }
-    ctx->bytes += (int64_t)bytes;
-    return GABI_OK;
-}
-
-void dev_free(gabi_ctx *ctx, void **p, size_t bytes) {
-    if (*p) {
-        (void)hipFree(*p);
-        ctx->bytes -= (int64_t)(bytes == 0 ? 8 : bytes);
-    }
-    *p = nullptr;
 }
 
 }  // namespace gabi
@@ -67,61 +47,240 @@ struct KeyHash {
     }
 };
 
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+namespace gabi {
+
+// Shared validation (also used by the batched solver and the server).
+int validate_surface(int64_t n, const double *cx, const double *cy, const double *cz,
+                     const double *nx, const double *ny, const double *nz,
+                     const double *area, std::string &msg) {
+    if (!cx || !cy || !cz || !nx || !ny || !nz || !area) {
+        msg = "null surface array";
+        return GABI_EINVAL;
+    }
+    if (n < 4) {
+        msg = "a closed surface needs at least 4 elements";
+        return GABI_EMESH;
+    }
+    if (n > (int64_t)INT32_MAX / 4) {
+        msg = "too many elements";
+        return GABI_EINVAL;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_finite(cx[i]) || !is_finite(cy[i]) || !is_finite(cz[i]) || !is_finite(nx[i]) ||
+            !is_finite(ny[i]) || !is_finite(nz[i]) || !is_finite(area[i])) {
+            msg = "non-finite element data at " + std::to_string(i);
+            return GABI_EMESH;
+        }
+        if (!(area[i] > 0.0)) {
+            msg = "element " + std::to_string(i) + " has area <= 0";
+            return GABI_EMESH;
+        }
+        const double nn = std::sqrt(nx[i] * nx[i] + ny[i] * ny[i] + nz[i] * nz[i]);
+        if (std::fabs(nn - 1.0) > 1e-6) {
+            msg = "normal of element " + std::to_string(i) + " is not unit";
+            return GABI_EMESH;
+        }
+    }
+    std::vector<int64_t> idx((size_t)n);
+    std::iota(idx.begin(), idx.end(), (int64_t)0);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        if (cx[a] != cx[b]) return cx[a] < cx[b];
+        if (cy[a] != cy[b]) return cy[a] < cy[b];
+        return cz[a] < cz[b];
+    });
+    for (int64_t t = 1; t < n; ++t) {
+        const int64_t a = idx[t - 1], b = idx[t];
+        if (cx[a] == cx[b] && cy[a] == cy[b] && cz[a] == cz[b]) {
+            msg = "elements " + std::to_string(a) + " and " + std::to_string(b) +
+                  " share a centroid";
+            return GABI_EMESH;
+        }
+    }
+    return GABI_OK;
+}
+
+int validate_charges(int64_t nc, const double *px, const double *py, const double *pz,
+                     const double *q, std::string &msg) {
+    if (nc < 0) {
+        msg = "negative charge count";
+        return GABI_EINVAL;
+    }
+    if (nc > 0 && (!px || !py || !pz || !q)) {
+        msg = "null charge array";
+        return GABI_EINVAL;
+    }
+    if (nc > (int64_t)INT32_MAX / 4) {
+        msg = "too many charges";
+        return GABI_EINVAL;
+    }
+    for (int64_t k = 0; k < nc; ++k)
+        if (!is_finite(px[k]) || !is_finite(py[k]) || !is_finite(pz[k]) || !is_finite(q[k])) {
+            msg = "non-finite charge data at " + std::to_string(k);
+            return GABI_EINVAL;
+        }
+    return GABI_OK;
+}
+
+// A charge exactly on a centroid makes a source term singular.
+int check_charges_vs_centroids(int64_t n, const double *cx, const double *cy,
+                               const double *cz, int64_t nc, const double *px,
+                               const double *py, const double *pz, std::string &msg) {
+    if (n == 0 || nc == 0) return GABI_OK;
+    std::unordered_set<Key, KeyHash> cent;
+    cent.reserve((size_t)n * 2);
+    for (int64_t i = 0; i < n; ++i) cent.insert(Key{cx[i], cy[i], cz[i]});
+    for (int64_t k = 0; k < nc; ++k)
+        if (cent.count(Key{px[k], py[k], pz[k]})) {
+            msg = "charge " + std::to_string(k) + " lies exactly on an element centroid";
+            return GABI_EINVAL;
+        }
+    return GABI_OK;
+}
+
+int params_valid(double eps1, double eps2, double kappa) {
+    return eps1 > 0.0 && eps2 > 0.0 && kappa >= 0.0 && std::isfinite(eps1) &&
+           std::isfinite(eps2) && std::isfinite(kappa);
+}
+
+int opts_check(const gabi_solve_opts *in, gabi_solve_opts *o, std::string &msg) {
+    gabi_default_opts(o);
+    if (in) *o = *in;
+    if (o->restart < 1 || o->restart > kMaxRestart) {
+        msg = "restart must be in [1, 64]";
+        return GABI_EINVAL;
+    }
+    if (o->maxit < 0) {
+        msg = "maxit must be >= 0";
+        return GABI_EINVAL;
+    }
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) {
+        msg = "tol must be > 0";
+        return GABI_EINVAL;
+    }
+    if (o->mode != GABI_SOLVE_FP64 && o->mode != GABI_SOLVE_MIXED_IR) {
+        msg = "unknown solve mode";
+        return GABI_EINVAL;
+    }
+    if (o->mode == GABI_SOLVE_MIXED_IR &&
+        (!(o->inner_tol > 0.0) || !(o->inner_tol < 1.0) || o->max_outer < 1)) {
+        msg = "need 0 < inner_tol < 1 and max_outer >= 1";
+        return GABI_EINVAL;
+    }
+    return GABI_OK;
+}
+
+// Upload of staged host data into a carved slot (synchronous on stream s).
+int upload_geometry(Slot &sl, const double4 *pos, const double4 *nrm, const float4 *nrm32,
+                    hipStream_t s) {
+    const int64_t n = sl.mol.n;
+    hipError_t e = hipMemcpyAsync((void *)sl.mol.pos, pos, sizeof(double4) * n,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void *)sl.mol.nrm, nrm, sizeof(double4) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void *)sl.mol.nrm32, nrm32, sizeof(float4) * n,
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? GABI_OK : GABI_EDEVICE;
+}
+
+int upload_charges(Slot &sl, const double *chg4, hipStream_t s) {
+    if (sl.mol.nc == 0) return GABI_OK;
+    hipError_t e = hipMemcpyAsync((void *)sl.mol.chg, chg4, sizeof(double4) * sl.mol.nc,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? GABI_OK : GABI_EDEVICE;
+}
+
+void stage_surface(int64_t n, const double *cx, const double *cy, const double *cz,
+                   const double *nx, const double *ny, const double *nz, const double *area,
+                   std::vector<double4> &pos, std::vector<double4> &nrm,
+                   std::vector<float4> &nrm32) {
+    pos.resize((size_t)n);
+    nrm.resize((size_t)n);
+    nrm32.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        pos[i] = make_double4(cx[i], cy[i], cz[i], area[i]);
+        nrm[i] = make_double4(nx[i], ny[i], nz[i], 0.0);
+        nrm32[i] = make_float4((float)nx[i], (float)ny[i], (float)nz[i], 0.0f);
+    }
+}
+
+}  // namespace gabi
+
+namespace {
+
 int use_device(gabi_ctx *ctx) {
     GABI_HIP(ctx, hipSetDevice(ctx->device));
     return GABI_OK;
 }
 
-// A charge exactly on a centroid makes a source term singular.
-int check_charges_vs_surface(gabi_ctx *ctx) {
-    if (ctx->n == 0 || ctx->nc == 0) return GABI_OK;
-    std::unordered_set<Key, KeyHash> cent;
-    cent.reserve((size_t)ctx->n * 2);
-    const double *c = ctx->host_centroids.data();
-    for (int64_t i = 0; i < ctx->n; ++i) cent.insert(Key{c[3 * i], c[3 * i + 1], c[3 * i + 2]});
-    const double *q = ctx->host_charges.data();
-    for (int64_t k = 0; k < ctx->nc; ++k) {
-        if (cent.count(Key{q[4 * k], q[4 * k + 1], q[4 * k + 2]}))
-            return fail(ctx, GABI_EINVAL,
-                        "charge " + std::to_string(k) + " lies exactly on an element centroid");
+void free_slot(gabi_ctx *ctx) {
+    if (ctx->slot.mem) (void)hipFree(ctx->slot.mem);
+    ctx->slot.mem = nullptr;
+    ctx->slot.bytes = 0;
+    ctx->slot_n = ctx->slot_nc = -1;
+    ctx->m_alloc = 0;
+    ctx->batch_dirty = true;
+}
+
+// Make the slot match the staged data (sizes, restart length), upload what
+// changed and rebuild the batch of one.
+int ensure_slot(gabi_ctx *ctx, int m) {
+    int rc = use_device(ctx);
+    if (rc) return rc;
+    m = std::max(m, std::max(ctx->m_alloc, 10));
+    if (!ctx->slot.mem || ctx->slot_n != ctx->n || ctx->slot_nc != ctx->nc || m > ctx->m_alloc) {
+        if (ctx->stream) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        free_slot(ctx);
+        const int64_t bytes = slot_bytes(ctx->n, ctx->nc, m);
+        hipError_t e = hipMalloc(&ctx->slot.mem, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->slot.mem = nullptr;
+            return fail(ctx, GABI_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                              " bytes failed");
+        }
+        ctx->slot.bytes = bytes;
+        slot_carve(ctx->slot, ctx->n, ctx->nc, m);
+        ctx->slot_n = ctx->n;
+        ctx->slot_nc = ctx->nc;
+        ctx->m_alloc = m;
+        ctx->geom_dirty = ctx->chg_dirty = true;
+        ctx->have_solution = false;
+        ctx->batch_dirty = true;
     }
+    if (ctx->geom_dirty) {
+        if (upload_geometry(ctx->slot, ctx->host_pos.data(), ctx->host_nrm.data(),
+                            ctx->host_nrm32.data(), ctx->stream))
+            return fail(ctx, GABI_EDEVICE, "geometry upload failed");
+        ctx->geom_dirty = false;
+    }
+    if (ctx->chg_dirty) {
+        if (upload_charges(ctx->slot, ctx->host_charges.data(), ctx->stream))
+            return fail(ctx, GABI_EDEVICE, "charge upload failed");
+        ctx->chg_dirty = false;
+    }
+    slot_set_params(ctx->slot, ctx->eps1, ctx->eps2, ctx->kappa);
     return GABI_OK;
 }
 
-void free_surface(gabi_ctx *ctx) {
-    const int64_t n = ctx->n, len = 2 * n;
-    dev_free(ctx, (void **)&ctx->pos, sizeof(double4) * n);
-    dev_free(ctx, (void **)&ctx->nrm, sizeof(double4) * n);
-    dev_free(ctx, (void **)&ctx->nrm32, sizeof(float4) * n);
-    dev_free(ctx, (void **)&ctx->wgt, sizeof(double4) * n);
-    dev_free(ctx, (void **)&ctx->wgt32, sizeof(float4) * n);
-    dev_free(ctx, (void **)&ctx->part, sizeof(double) * ctx->part_len);
-    ctx->part_len = 0;
-    dev_free(ctx, (void **)&ctx->vec_u, sizeof(double) * len);
-    dev_free(ctx, (void **)&ctx->vec_y, sizeof(double) * len);
-    dev_free(ctx, (void **)&ctx->vec_b, sizeof(double) * len);
-    dev_free(ctx, (void **)&ctx->vec_in, sizeof(double) * len);
-    if (ctx->V) {
-        const int m = ctx->kry_m;
-        dev_free(ctx, (void **)&ctx->V, sizeof(double) * len * (m + 1));
-        dev_free(ctx, (void **)&ctx->H, sizeof(double) * (m + 1) * m);
-        dev_free(ctx, (void **)&ctx->givens, sizeof(double) * (4 * m + 1));
-        ctx->kry_m = 0;
-    }
-    double **vs[] = {&ctx->gm_b, &ctx->gm_x, &ctx->gm_r, &ctx->gm_w, &ctx->ir_x, &ctx->ir_r};
-    for (double **p : vs) dev_free(ctx, (void **)p, sizeof(double) * len);
-    ctx->n = 0;
-    ctx->have_solution = false;
-    ctx->host_centroids.clear();
-}
-
-void free_charges(gabi_ctx *ctx) {
-    dev_free(ctx, (void **)&ctx->chg, sizeof(double4) * ctx->nc);
-    dev_free(ctx, (void **)&ctx->phi_dev, sizeof(double) * ctx->nc);
-    dev_free(ctx, (void **)&ctx->phi_part, sizeof(double) * ctx->phi_part_len);
-    ctx->phi_part_len = 0;
-    ctx->nc = 0;
-    ctx->host_charges.clear();
+int sync_batch(gabi_ctx *ctx) {
+    if (!ctx->batch_dirty && ctx->batch.d_mem &&
+        std::memcmp(&ctx->uploaded, &ctx->slot.mol, sizeof(Mol)) == 0)
+        return GABI_OK;  // descriptor unchanged: keep the batch and its graph
+    ctx->batch.slots.assign(1, &ctx->slot);
+    ctx->batch.mode = ctx->slot.mol.mode;
+    std::string err;
+    int rc = batch_build(ctx->batch, ctx->stream, err);
+    if (rc) return fail(ctx, rc, err);
+    ctx->uploaded = ctx->slot.mol;
+    ctx->batch_dirty = false;
+    return GABI_OK;
 }
 
 int require_state(gabi_ctx *ctx, bool need_charges) {
@@ -129,10 +288,31 @@ int require_state(gabi_ctx *ctx, bool need_charges) {
     if (ctx->n == 0) return fail(ctx, GABI_ESTATE, "surface not set");
     if (!ctx->params_set) return fail(ctx, GABI_ESTATE, "parameters not set");
     if (need_charges && !ctx->charges_set) return fail(ctx, GABI_ESTATE, "charges not set");
-    return use_device(ctx);
+    return GABI_OK;
 }
 
-bool is_finite(double v) { return std::isfinite(v); }
+int prepare(gabi_ctx *ctx, bool need_charges, int m) {
+    int rc = require_state(ctx, need_charges);
+    if (rc) return rc;
+    if ((rc = ensure_slot(ctx, m))) return rc;
+    return sync_batch(ctx);
+}
+
+Timer make_timer(gabi_ctx *ctx) {
+    Timer t;
+    if (ctx->timing) {
+        t.pending[0] = &ctx->pending[0];
+        t.pending[1] = &ctx->pending[1];
+    }
+    return t;
+}
+
+int read_status(gabi_ctx *ctx) {
+    enqueue_gather(ctx->batch, ctx->stream);
+    GABI_HIP(ctx, hipGetLastError());
+    GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GABI_OK;
+}
 
 }  // namespace
 
@@ -145,7 +325,7 @@ void gabi_default_opts(gabi_solve_opts *o) {
     o->tol = 1e-6;
     o->mode = GABI_SOLVE_FP64;
     o->inner_tol = 1e-5;
-    o->max_outer = 10;
+    o->max_outer = 20;
     o->use_graph = 1;
 }
 
@@ -157,17 +337,13 @@ int gabi_create(gabi_ctx **out, int device) {
         (void)hipGetLastError();
         return GABI_EDEVICE;
     }
+    if (hipSetDevice(device) != hipSuccess) return GABI_EDEVICE;
     gabi_ctx *ctx = new (std::nothrow) gabi_ctx();
     if (!ctx) return GABI_ENOMEM;
     ctx->device = device;
-    if (hipSetDevice(device) != hipSuccess) {
-        delete ctx;
-        return GABI_EDEVICE;
-    }
-    if (dev_alloc(ctx, (void **)&ctx->red, sizeof(double) * 2 * kBlasBlocksMax) ||
-        dev_alloc(ctx, (void **)&ctx->scalars, sizeof(double) * 16)) {
-        gabi_destroy(ctx);
-        return GABI_ENOMEM;
+    if (hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->capture = nullptr;  // graphs unavailable; rounds run eagerly
     }
     *out = ctx;
     return GABI_OK;
@@ -179,16 +355,13 @@ void gabi_destroy(gabi_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     for (int p = 0; p < 2; ++p)
-        for (auto &ev : ctx->timing.pending[p]) {
+        for (auto &ev : ctx->pending[p]) {
             (void)hipEventDestroy(ev.first);
             (void)hipEventDestroy(ev.second);
         }
-    free_surface(ctx);
-    free_charges(ctx);
-    dev_free(ctx, (void **)&ctx->red, 0);
-    dev_free(ctx, (void **)&ctx->scalars, 0);
-    dev_free(ctx, (void **)&ctx->status, 0);
-    if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+    batch_free(ctx->batch);
+    free_slot(ctx);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     delete ctx;
 }
 
@@ -236,88 +409,31 @@ int gabi_set_surface(gabi_ctx *ctx, int64_t n, const double *cx,
                      const double *cy, const double *cz, const double *nx,
                      const double *ny, const double *nz, const double *area) {
     if (!ctx) return GABI_EINVAL;
-    if (!cx || !cy || !cz || !nx || !ny || !nz || !area)
-        return fail(ctx, GABI_EINVAL, "null surface array");
-    if (n < 4) return fail(ctx, GABI_EMESH, "a closed surface needs at least 4 elements");
-    if (n > (int64_t)INT32_MAX / 2)
-        return fail(ctx, GABI_EINVAL, "too many elements");
-    for (int64_t i = 0; i < n; ++i) {
-        if (!is_finite(cx[i]) || !is_finite(cy[i]) || !is_finite(cz[i]) || !is_finite(nx[i]) ||
-            !is_finite(ny[i]) || !is_finite(nz[i]) || !is_finite(area[i]))
-            return fail(ctx, GABI_EMESH, "non-finite element data at " + std::to_string(i));
-        if (!(area[i] > 0.0))
-            return fail(ctx, GABI_EMESH, "element " + std::to_string(i) + " has area <= 0");
-        const double nn = std::sqrt(nx[i] * nx[i] + ny[i] * ny[i] + nz[i] * nz[i]);
-        if (std::fabs(nn - 1.0) > 1e-6)
-            return fail(ctx, GABI_EMESH, "normal of element " + std::to_string(i) + " is not unit");
-    }
-    {   // duplicate centroids: lexicographic sort, compare neighbours
-        std::vector<int64_t> idx((size_t)n);
-        std::iota(idx.begin(), idx.end(), (int64_t)0);
-        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-            if (cx[a] != cx[b]) return cx[a] < cx[b];
-            if (cy[a] != cy[b]) return cy[a] < cy[b];
-            return cz[a] < cz[b];
-        });
-        for (int64_t t = 1; t < n; ++t) {
-            const int64_t a = idx[t - 1], b = idx[t];
-            if (cx[a] == cx[b] && cy[a] == cy[b] && cz[a] == cz[b])
-                return fail(ctx, GABI_EMESH, "elements " + std::to_string(a) + " and " +
-                                                 std::to_string(b) + " share a centroid");
-        }
-    }
-    std::vector<double> cent((size_t)(3 * n));
-    for (int64_t i = 0; i < n; ++i) {
-        cent[3 * i] = cx[i];
-        cent[3 * i + 1] = cy[i];
-        cent[3 * i + 2] = cz[i];
-    }
+    std::string msg;
+    int rc = validate_surface(n, cx, cy, cz, nx, ny, nz, area, msg);
+    if (rc) return fail(ctx, rc, msg);
     if (ctx->nc > 0) {
-        std::swap(ctx->host_centroids, cent);
-        const int64_t keep = ctx->n;
-        ctx->n = n;
-        int rc = check_charges_vs_surface(ctx);
-        ctx->n = keep;
-        std::swap(ctx->host_centroids, cent);
-        if (rc) return rc;
+        const double *q = ctx->host_charges.data();
+        std::vector<double> px(ctx->nc), py(ctx->nc), pz(ctx->nc);
+        for (int64_t k = 0; k < ctx->nc; ++k) {
+            px[k] = q[4 * k];
+            py[k] = q[4 * k + 1];
+            pz[k] = q[4 * k + 2];
+        }
+        rc = check_charges_vs_centroids(n, cx, cy, cz, ctx->nc, px.data(), py.data(),
+                                        pz.data(), msg);
+        if (rc) return fail(ctx, rc, msg);
     }
-    int rc = use_device(ctx);
-    if (rc) return rc;
-
-    // host staging in the device layout
-    std::vector<double4> hp((size_t)n), hn((size_t)n);
-    std::vector<float4> hn32((size_t)n);
+    stage_surface(n, cx, cy, cz, nx, ny, nz, area, ctx->host_pos, ctx->host_nrm,
+                  ctx->host_nrm32);
+    ctx->host_centroids.resize((size_t)(3 * n));
     for (int64_t i = 0; i < n; ++i) {
-        hp[i] = make_double4(cx[i], cy[i], cz[i], area[i]);
-        hn[i] = make_double4(nx[i], ny[i], nz[i], 0.0);
-        hn32[i] = make_float4((float)nx[i], (float)ny[i], (float)nz[i], 0.0f);
-    }
-    if (ctx->stream) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    free_surface(ctx);
-    const int64_t len = 2 * n;
-    const PairLaunch L64 = pair_launch(n, GABI_FP64), L32 = pair_launch(n, GABI_FP32_PAIR);
-    const int64_t part_len = 2 * n * (int64_t)std::max(L64.splits, L32.splits);
-    if ((rc = dev_alloc(ctx, (void **)&ctx->pos, sizeof(double4) * n)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->nrm, sizeof(double4) * n)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->nrm32, sizeof(float4) * n)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->wgt, sizeof(double4) * n)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->wgt32, sizeof(float4) * n)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->part, sizeof(double) * part_len)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->vec_u, sizeof(double) * len)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->vec_y, sizeof(double) * len)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->vec_b, sizeof(double) * len)) ||
-        (rc = dev_alloc(ctx, (void **)&ctx->vec_in, sizeof(double) * len))) {
-        ctx->n = n;  // so that free_surface releases what was allocated
-        ctx->part_len = part_len;
-        free_surface(ctx);
-        return rc;
+        ctx->host_centroids[3 * i] = cx[i];
+        ctx->host_centroids[3 * i + 1] = cy[i];
+        ctx->host_centroids[3 * i + 2] = cz[i];
     }
     ctx->n = n;
-    ctx->part_len = part_len;
-    GABI_HIP(ctx, hipMemcpy(ctx->pos, hp.data(), sizeof(double4) * n, hipMemcpyHostToDevice));
-    GABI_HIP(ctx, hipMemcpy(ctx->nrm, hn.data(), sizeof(double4) * n, hipMemcpyHostToDevice));
-    GABI_HIP(ctx, hipMemcpy(ctx->nrm32, hn32.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
-    ctx->host_centroids.swap(cent);
+    ctx->geom_dirty = true;
     ctx->have_solution = false;
     return GABI_OK;
 }
@@ -340,51 +456,37 @@ int gabi_set_surface_mesh(gabi_ctx *ctx, int64_t nv, const double *xyz,
 int gabi_set_charges(gabi_ctx *ctx, int64_t nc, const double *px,
                      const double *py, const double *pz, const double *q) {
     if (!ctx) return GABI_EINVAL;
-    if (nc < 0) return fail(ctx, GABI_EINVAL, "negative charge count");
-    if (nc > 0 && (!px || !py || !pz || !q)) return fail(ctx, GABI_EINVAL, "null charge array");
-    if (nc > (int64_t)INT32_MAX / 2) return fail(ctx, GABI_EINVAL, "too many charges");
-    std::vector<double> h((size_t)(4 * nc));
-    for (int64_t k = 0; k < nc; ++k) {
-        if (!is_finite(px[k]) || !is_finite(py[k]) || !is_finite(pz[k]) || !is_finite(q[k]))
-            return fail(ctx, GABI_EINVAL, "non-finite charge data at " + std::to_string(k));
-        h[4 * k] = px[k];
-        h[4 * k + 1] = py[k];
-        h[4 * k + 2] = pz[k];
-        h[4 * k + 3] = q[k];
-    }
+    std::string msg;
+    int rc = validate_charges(nc, px, py, pz, q, msg);
+    if (rc) return fail(ctx, rc, msg);
     if (ctx->n > 0 && nc > 0) {
-        std::swap(ctx->host_charges, h);
-        const int64_t keep = ctx->nc;
-        ctx->nc = nc;
-        int rc = check_charges_vs_surface(ctx);
-        ctx->nc = keep;
-        std::swap(ctx->host_charges, h);
-        if (rc) return rc;
-    }
-    int rc = use_device(ctx);
-    if (rc) return rc;
-    if (ctx->stream) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    free_charges(ctx);
-    if (nc > 0) {
-        if ((rc = dev_alloc(ctx, (void **)&ctx->chg, sizeof(double4) * nc)) ||
-            (rc = dev_alloc(ctx, (void **)&ctx->phi_dev, sizeof(double) * nc))) {
-            ctx->nc = nc;
-            free_charges(ctx);
-            return rc;
+        const int64_t n = ctx->n;
+        std::vector<double> cx(n), cy(n), cz(n);
+        for (int64_t i = 0; i < n; ++i) {
+            cx[i] = ctx->host_centroids[3 * i];
+            cy[i] = ctx->host_centroids[3 * i + 1];
+            cz[i] = ctx->host_centroids[3 * i + 2];
         }
-        GABI_HIP(ctx, hipMemcpy(ctx->chg, h.data(), sizeof(double4) * nc, hipMemcpyHostToDevice));
+        rc = check_charges_vs_centroids(n, cx.data(), cy.data(), cz.data(), nc, px, py, pz, msg);
+        if (rc) return fail(ctx, rc, msg);
+    }
+    ctx->host_charges.resize((size_t)(4 * nc));
+    for (int64_t k = 0; k < nc; ++k) {
+        ctx->host_charges[4 * k] = px[k];
+        ctx->host_charges[4 * k + 1] = py[k];
+        ctx->host_charges[4 * k + 2] = pz[k];
+        ctx->host_charges[4 * k + 3] = q[k];
     }
     ctx->nc = nc;
-    ctx->host_charges.swap(h);
     ctx->charges_set = true;
+    ctx->chg_dirty = true;
     ctx->have_solution = false;
     return GABI_OK;
 }
 
 int gabi_set_params(gabi_ctx *ctx, double eps1, double eps2, double kappa) {
     if (!ctx) return GABI_EINVAL;
-    if (!(eps1 > 0.0) || !(eps2 > 0.0) || !(kappa >= 0.0) || !is_finite(eps1) ||
-        !is_finite(eps2) || !is_finite(kappa))
+    if (!params_valid(eps1, eps2, kappa))
         return fail(ctx, GABI_EINVAL, "need eps1 > 0, eps2 > 0, kappa >= 0, all finite");
     ctx->eps1 = eps1;
     ctx->eps2 = eps2;
@@ -395,140 +497,167 @@ int gabi_set_params(gabi_ctx *ctx, double eps1, double eps2, double kappa) {
 }
 
 int gabi_rhs_dev(gabi_ctx *ctx, double *b_dev) {
-    int rc = require_state(ctx, true);
+    int rc = prepare(ctx, true, 0);
     if (rc) return rc;
     if (!b_dev) return fail(ctx, GABI_EINVAL, "null output");
-    launch_rhs(ctx, b_dev);
+    launch_rhs(ctx->batch, ctx->stream);
+    GABI_HIP(ctx, hipMemcpyAsync(b_dev, ctx->slot.mol.rhs_dst, sizeof(double) * 2 * ctx->n,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
     GABI_HIP(ctx, hipGetLastError());
     return GABI_OK;
 }
 
 int gabi_rhs(gabi_ctx *ctx, double *b) {
-    int rc = require_state(ctx, true);
+    int rc = prepare(ctx, true, 0);
     if (rc) return rc;
     if (!b) return fail(ctx, GABI_EINVAL, "null output");
-    launch_rhs(ctx, ctx->vec_y);
+    launch_rhs(ctx->batch, ctx->stream);
     GABI_HIP(ctx, hipGetLastError());
-    GABI_HIP(ctx, hipMemcpyAsync(b, ctx->vec_y, sizeof(double) * 2 * ctx->n,
+    GABI_HIP(ctx, hipMemcpyAsync(b, ctx->slot.mol.rhs_dst, sizeof(double) * 2 * ctx->n,
                                  hipMemcpyDeviceToHost, ctx->stream));
     GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return GABI_OK;
 }
 
-int gabi_matvec_dev(gabi_ctx *ctx, int precision, const double *u_dev,
-                    double *y_dev) {
-    int rc = require_state(ctx, false);
+static int matvec_impl(gabi_ctx *ctx, int precision, const void *u, double *y,
+                       hipMemcpyKind in_kind, hipMemcpyKind out_kind) {
+    int rc = prepare(ctx, false, 0);
     if (rc) return rc;
     if (precision != GABI_FP64 && precision != GABI_FP32_PAIR)
         return fail(ctx, GABI_EINVAL, "unknown precision");
-    if (!u_dev || !y_dev) return fail(ctx, GABI_EINVAL, "null vector");
-    return matvec_device(ctx, precision, u_dev, y_dev);
+    if (!u || !y) return fail(ctx, GABI_EINVAL, "null vector");
+    const size_t bytes = sizeof(double) * 2 * ctx->n;
+    GABI_HIP(ctx, hipMemcpyAsync(ctx->slot.mol.u, u, bytes, in_kind, ctx->stream));
+    Timer t = make_timer(ctx);
+    launch_prep(ctx->batch, ctx->stream, precision, kPrepU, 0, false);
+    launch_pair(ctx->batch, ctx->stream, precision, false, &t);
+    launch_finish(ctx->batch, ctx->stream, precision, kFinishY, 0, false);
+    GABI_HIP(ctx, hipGetLastError());
+    GABI_HIP(ctx, hipMemcpyAsync(y, ctx->slot.mol.y, bytes, out_kind, ctx->stream));
+    if (out_kind == hipMemcpyDeviceToHost) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GABI_OK;
+}
+
+int gabi_matvec_dev(gabi_ctx *ctx, int precision, const double *u_dev, double *y_dev) {
+    return matvec_impl(ctx, precision, u_dev, y_dev, hipMemcpyDeviceToDevice,
+                       hipMemcpyDeviceToDevice);
 }
 
 int gabi_matvec(gabi_ctx *ctx, int precision, const double *u, double *y) {
-    int rc = require_state(ctx, false);
-    if (rc) return rc;
-    if (!u || !y) return fail(ctx, GABI_EINVAL, "null vector");
-    const size_t bytes = sizeof(double) * 2 * ctx->n;
-    GABI_HIP(ctx, hipMemcpyAsync(ctx->vec_in, u, bytes, hipMemcpyHostToDevice, ctx->stream));
-    if ((rc = gabi_matvec_dev(ctx, precision, ctx->vec_in, ctx->vec_y))) return rc;
-    GABI_HIP(ctx, hipMemcpyAsync(y, ctx->vec_y, bytes, hipMemcpyDeviceToHost, ctx->stream));
-    GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return GABI_OK;
+    return matvec_impl(ctx, precision, u, y, hipMemcpyHostToDevice, hipMemcpyDeviceToHost);
 }
 
-static int check_opts(gabi_ctx *ctx, const gabi_solve_opts *in, gabi_solve_opts *o) {
-    gabi_default_opts(o);
-    if (in) *o = *in;
-    if (o->restart < 1 || o->restart > 64)
-        return fail(ctx, GABI_EINVAL, "restart must be in [1, 64]");
-    if (o->maxit < 0) return fail(ctx, GABI_EINVAL, "maxit must be >= 0");
-    if (!(o->tol > 0.0) || !is_finite(o->tol)) return fail(ctx, GABI_EINVAL, "tol must be > 0");
-    if (o->mode != GABI_SOLVE_FP64 && o->mode != GABI_SOLVE_MIXED_IR)
-        return fail(ctx, GABI_EINVAL, "unknown solve mode");
-    if (o->mode == GABI_SOLVE_MIXED_IR &&
-        (!(o->inner_tol > 0.0) || !(o->inner_tol < 1.0) || o->max_outer < 1))
-        return fail(ctx, GABI_EINVAL, "need 0 < inner_tol < 1 and max_outer >= 1");
-    return GABI_OK;
+static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0,
+                      hipMemcpyKind x0_kind, double *u, hipMemcpyKind u_kind,
+                      gabi_solve_info *info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    gabi_solve_opts o;
+    std::string msg;
+    int rc = require_state(ctx, true);
+    if (rc) return rc;
+    if ((rc = opts_check(opts, &o, msg))) return fail(ctx, rc, msg);
+    if ((rc = ensure_slot(ctx, o.restart))) return rc;
+    Slot &sl = ctx->slot;
+    const int mode = o.mode == GABI_SOLVE_MIXED_IR ? kModeMixed : kModeFP64;
+    slot_set_mode(sl, mode);
+    set_solve_targets(sl, o.tol, o.inner_tol, o.maxit);
+    sl.mol.m = o.restart;
+    if ((rc = sync_batch(ctx))) return rc;
+    Batch &b = ctx->batch;
+    Timer t = make_timer(ctx);
+    const bool graph = o.use_graph && !ctx->timing;
+    const size_t bytes = sizeof(double) * 2 * ctx->n;
+    if (x0)
+        GABI_HIP(ctx, hipMemcpyAsync(sl.mol.res_x, x0, bytes, x0_kind, ctx->stream));
+    enqueue_init(b, ctx->stream, x0 != nullptr, &t);
+    if ((rc = read_status(ctx))) return rc;
+    int rounds = 0;
+    for (;;) {
+        const KrylovStatus &st = b.h_status[0];
+        if (st.converged || st.iters >= st.maxit) break;
+        if (mode == kModeMixed && rounds >= o.max_outer) break;
+        if ((rc = run_round(b, ctx->stream, ctx->capture, &t, graph, msg)))
+            return fail(ctx, rc, msg);
+        if ((rc = read_status(ctx))) return rc;
+        ++rounds;
+    }
+    enqueue_finalize(b, ctx->stream);  // solution to sol, reaction potential, energy
+    if (u) GABI_HIP(ctx, hipMemcpyAsync(u, sl.mol.sol, bytes, u_kind, ctx->stream));
+    if ((rc = read_status(ctx))) return rc;
+    const KrylovStatus &st = b.h_status[0];
+    gabi_solve_info out{};
+    out.iterations = st.iters;
+    out.restarts = rounds;
+    const int64_t extra = x0 ? 1 : 0;
+    if (mode == kModeMixed) {
+        out.matvecs_fp32 = st.iters;
+        out.matvecs_fp64 = rounds + extra;
+        out.outer = rounds;
+    } else {
+        out.matvecs_fp64 = st.iters + rounds + extra;
+    }
+    out.rel_residual = st.beta0 > 0 ? st.rnorm / st.beta0 : 0.0;
+    out.converged = st.converged;
+    out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = out;
+    ctx->have_solution = true;
+    return out.converged ? GABI_OK : GABI_NOT_CONVERGED;
 }
 
 int gabi_solve_dev(gabi_ctx *ctx, const gabi_solve_opts *opts,
                    const double *x0_dev, double *u_dev, gabi_solve_info *info) {
-    int rc = require_state(ctx, true);
-    if (rc) return rc;
-    gabi_solve_opts o;
-    if ((rc = check_opts(ctx, opts, &o))) return rc;
-    return solve_device(ctx, o, x0_dev, u_dev, info);
+    return solve_impl(ctx, opts, x0_dev, hipMemcpyDeviceToDevice, u_dev,
+                      hipMemcpyDeviceToDevice, info);
 }
 
 int gabi_solve(gabi_ctx *ctx, const gabi_solve_opts *opts, const double *x0,
                double *u, gabi_solve_info *info) {
-    int rc = require_state(ctx, true);
-    if (rc) return rc;
-    gabi_solve_opts o;
-    if ((rc = check_opts(ctx, opts, &o))) return rc;
-    const size_t bytes = sizeof(double) * 2 * ctx->n;
-    if (x0)
-        GABI_HIP(ctx, hipMemcpyAsync(ctx->vec_in, x0, bytes, hipMemcpyHostToDevice, ctx->stream));
-    rc = solve_device(ctx, o, x0 ? ctx->vec_in : nullptr, nullptr, info);
-    if (rc < 0) return rc;
-    if (u) {
-        GABI_HIP(ctx, hipMemcpyAsync(u, ctx->vec_u, bytes, hipMemcpyDeviceToHost, ctx->stream));
-        GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    }
-    return rc;
+    return solve_impl(ctx, opts, x0, hipMemcpyHostToDevice, u, hipMemcpyDeviceToHost, info);
 }
 
-static int energy_impl(gabi_ctx *ctx, const double *u_dev, double *e, double *phi_host) {
-    if (!u_dev) {
-        if (!ctx->have_solution) return fail(ctx, GABI_ESTATE, "no solution to evaluate");
-        u_dev = ctx->vec_u;
-    }
-    launch_prep(ctx, GABI_FP64, u_dev, nullptr, nullptr, nullptr);
-    int rc = launch_reaction(ctx, ctx->nc ? ctx->phi_dev : nullptr, ctx->scalars);
+static int energy_impl(gabi_ctx *ctx, const void *u, hipMemcpyKind kind, double *e,
+                       double *phi_host) {
+    int rc = prepare(ctx, true, 0);
     if (rc) return rc;
-    if (e)
-        GABI_HIP(ctx, hipMemcpyAsync(e, ctx->scalars, sizeof(double), hipMemcpyDeviceToHost,
+    if (u) {
+        GABI_HIP(ctx, hipMemcpyAsync(ctx->slot.mol.u, u, sizeof(double) * 2 * ctx->n, kind,
                                      ctx->stream));
+        launch_prep(ctx->batch, ctx->stream, GABI_FP64, kPrepU, 0, false);
+    } else {
+        if (!ctx->have_solution) return fail(ctx, GABI_ESTATE, "no solution to evaluate");
+        launch_prep(ctx->batch, ctx->stream, GABI_FP64, kPrepSol, 0, false);
+    }
+    launch_reaction(ctx->batch, ctx->stream);
     if (phi_host && ctx->nc)
-        GABI_HIP(ctx, hipMemcpyAsync(phi_host, ctx->phi_dev, sizeof(double) * ctx->nc,
+        GABI_HIP(ctx, hipMemcpyAsync(phi_host, ctx->slot.mol.phi, sizeof(double) * ctx->nc,
                                      hipMemcpyDeviceToHost, ctx->stream));
-    GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if ((rc = read_status(ctx))) return rc;
+    if (e) *e = ctx->batch.h_status[0].energy;
     return GABI_OK;
 }
 
 int gabi_energy_dev(gabi_ctx *ctx, const double *u_dev, double *e) {
-    int rc = require_state(ctx, true);
-    if (rc) return rc;
-    if (!e) return fail(ctx, GABI_EINVAL, "null output");
-    return energy_impl(ctx, u_dev, e, nullptr);
+    if (ctx && !e) return fail(ctx, GABI_EINVAL, "null output");
+    return energy_impl(ctx, u_dev, hipMemcpyDeviceToDevice, e, nullptr);
 }
 
 int gabi_energy(gabi_ctx *ctx, const double *u, double *e) {
-    int rc = require_state(ctx, true);
-    if (rc) return rc;
-    if (!e) return fail(ctx, GABI_EINVAL, "null output");
-    if (u)
-        GABI_HIP(ctx, hipMemcpyAsync(ctx->vec_in, u, sizeof(double) * 2 * ctx->n,
-                                     hipMemcpyHostToDevice, ctx->stream));
-    return energy_impl(ctx, u ? ctx->vec_in : nullptr, e, nullptr);
+    if (ctx && !e) return fail(ctx, GABI_EINVAL, "null output");
+    return energy_impl(ctx, u, hipMemcpyHostToDevice, e, nullptr);
 }
 
 int gabi_reaction_potential(gabi_ctx *ctx, const double *u, double *phi) {
-    int rc = require_state(ctx, true);
-    if (rc) return rc;
-    if (!phi && ctx->nc) return fail(ctx, GABI_EINVAL, "null output");
-    if (u)
-        GABI_HIP(ctx, hipMemcpyAsync(ctx->vec_in, u, sizeof(double) * 2 * ctx->n,
-                                     hipMemcpyHostToDevice, ctx->stream));
-    return energy_impl(ctx, u ? ctx->vec_in : nullptr, nullptr, phi);
+    if (ctx && !phi && ctx->nc) return fail(ctx, GABI_EINVAL, "null output");
+    return energy_impl(ctx, u, hipMemcpyHostToDevice, nullptr, phi);
 }
 
-int64_t gabi_device_bytes(const gabi_ctx *ctx) { return ctx ? ctx->bytes : 0; }
+int64_t gabi_device_bytes(const gabi_ctx *ctx) {
+    return ctx ? ctx->slot.bytes + ctx->batch.cap_bytes : 0;
+}
 
 int gabi_set_kernel_timing(gabi_ctx *ctx, int enable) {
     if (!ctx) return GABI_EINVAL;
-    ctx->timing.enabled = enable != 0;
+    ctx->timing = enable != 0;
     return GABI_OK;
 }
 
@@ -538,22 +667,21 @@ int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
     if (precision != GABI_FP64 && precision != GABI_FP32_PAIR)
         return fail(ctx, GABI_EINVAL, "unknown precision");
     const int p = precision == GABI_FP64 ? 0 : 1;
-    Timing &t = ctx->timing;
-    for (auto &ev : t.pending[p]) {
+    for (auto &ev : ctx->pending[p]) {
         GABI_HIP(ctx, hipEventSynchronize(ev.second));
         float ms = 0.0f;
         GABI_HIP(ctx, hipEventElapsedTime(&ms, ev.first, ev.second));
-        t.total_ms[p] += ms;
-        t.count[p] += 1;
+        ctx->total_ms[p] += ms;
+        ctx->count[p] += 1;
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
     }
-    t.pending[p].clear();
-    if (avg_ms) *avg_ms = t.count[p] ? t.total_ms[p] / (double)t.count[p] : 0.0;
-    if (count) *count = t.count[p];
+    ctx->pending[p].clear();
+    if (avg_ms) *avg_ms = ctx->count[p] ? ctx->total_ms[p] / (double)ctx->count[p] : 0.0;
+    if (count) *count = ctx->count[p];
     if (reset) {
-        t.total_ms[p] = 0.0;
-        t.count[p] = 0;
+        ctx->total_ms[p] = 0.0;
+        ctx->count[p] = 0;
     }
     return GABI_OK;
 }

@@ -1,5 +1,10 @@
-// Internal declarations of libgabi: device buffers, launch configuration
-// and kernel launchers shared by the C-ABI layer and the Krylov driver.
+// Internal declarations of libgabi.
+//
+// Every kernel works on a *batch* of molecules described by an array of
+// `Mol` records in device memory; a workgroup finds its molecule (and its
+// block within that molecule) in a per-launch block list built on the host.
+// A single solve is a batch of one, so a molecule is decomposed, reduced and
+// iterated identically whether it runs alone or among others.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -13,13 +18,14 @@ namespace gabi {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kTile = 256;           // sources staged in LDS per tile
-constexpr int kBlasBlocksMax = 256;  // blocks of the reduction kernels
+constexpr int kBlasBlocksMax = 256;  // workgroups per molecule in reductions
+constexpr int kMaxRestart = 64;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kCoulomb = 332.0716;  // kcal A / (mol e^2)
 
+// ---------------------------------------------------------------------------
 // Decomposition of one product: row blocks x source splits.  A function of
-// N and the precision only, so every product of the same size sums in the
-// same order (bitwise reproducible, independent of other work).
+// N and the precision (and the loaded tuning table) only.
 struct PairLaunch {
     int rows_per_thread = 1;
     int row_blocks = 0;
@@ -27,85 +33,146 @@ struct PairLaunch {
     int splits = 0;
 };
 
+struct TuneEntry {  // one row of the tuning table
+    int rows_per_thread = 2;
+    int target_blocks = 2048;
+};
+
 PairLaunch pair_launch(int64_t n, int precision);
+int blas_blocks(int64_t n);
+// Tuning table (tune.hip): per precision and N bucket (bucket = floor(log2 N)).
+TuneEntry tune_entry(int precision, int64_t n);
+int set_tune_entry(int precision, int bucket, TuneEntry e);
+void reset_tuning();
 
-// Device status of one GMRES run (see krylov.hip).
+// ---------------------------------------------------------------------------
+// Device status of one molecule's solve.
 struct KrylovStatus {
-    int32_t k;       // Arnoldi steps taken in the current cycle
-    int32_t done;    // cycle ended (estimate below tol, breakdown, maxit)
-    int32_t iters;   // Arnoldi steps of this run
+    int32_t k;          // Arnoldi steps taken in the current cycle
+    int32_t done;       // current cycle ended (estimate, breakdown, cap)
+    int32_t iters;      // Arnoldi steps of the whole solve
     int32_t maxit;
-    double beta;     // ||b||
-    double tol;
-    double rnorm;    // ||r|| of the last explicit residual
-    double gabs;     // |g_k|, the Givens estimate of ||r||
+    int32_t converged;  // explicit residual <= tol0 * beta0
+    int32_t pad[3];
+    double beta0;       // ||b|| of the Poisson-Boltzmann right-hand side
+    double beta;        // norm the current cycle's estimate is relative to
+    double tol;         // estimate threshold (relative to beta)
+    double tol0;        // final tolerance (relative to beta0)
+    double inner_tol;   // mixed refinement: relative target of one cycle
+    double rnorm;       // last explicit residual norm
+    double gabs;        // |g_k|, the Givens estimate
+    double energy;      // solvation energy (kcal/mol) after launch_reaction
 };
 
-struct Timing {
-    bool enabled = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
-    double total_ms[2] = {0, 0};
-    int64_t count[2] = {0, 0};
+enum SolveMode { kModeFP64 = 0, kModeMixed = 1 };
+
+// Device-visible description of one molecule (plain data).
+struct Mol {
+    int32_t n, nc, nb, m;
+    int32_t mode;
+    int32_t R64, rb64, tps64, sp64;   // FP64 product decomposition
+    int32_t R32, rb32, tps32, sp32;   // FP32-pair product decomposition
+    int32_t rx_kblocks, rx_tps, rx_splits, maxit;
+    double kappa, eps, inv_eps, d_top, d_bot, rhs_scale;
+    double tol0, inner_tol;             // solve targets (copied into st)
+    float kappa_f, nkl2e_f, eps_f, inv_eps_f;
+    const double4 *pos;   // (cx, cy, cz, area)
+    const double4 *nrm;   // (nx, ny, nz, 0)
+    const float4 *nrm32;
+    const double4 *chg;   // (x, y, z, q)
+    double4 *wgt;         // (s, mx, my, mz)
+    float4 *wgt32;
+    double *part;         // split partial sums [splits][2][n]
+    // vectors of length 2n
+    double *u, *y;        // product input / output (matvec entry points)
+    double *b, *x, *r, *w, *bo, *xo, *sol;
+    // role pointers set by the solve mode (see krylov.hip)
+    double *rhs_dst, *cyc_src, *upd_dst, *res_x, *res_b, *res_out;
+    // Krylov
+    double *V, *H, *cs, *sn, *g, *hn, *red;
+    KrylovStatus *st;
+    // reaction potential at the charges
+    double *phi, *phi_part;
 };
+
+// Host-side record of one molecule: its descriptor plus bookkeeping.
+struct Slot {
+    Mol mol{};
+    void *mem = nullptr;      // one device block holding every buffer
+    int64_t bytes = 0;
+    bool from_arena = false;
+    int64_t arena_off = 0;
+    // solve bookkeeping
+    int64_t tag = 0;
+    int32_t rounds = 0;
+    int64_t products64 = 0, products32 = 0;
+    int32_t last_iters = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    double *u_out = nullptr;  // caller's host buffer for the solution
+    int status = 0;
+};
+
+// Size of the device block of a slot and the carving of its buffers.
+int64_t slot_bytes(int64_t n, int64_t nc, int m);
+void slot_carve(Slot &s, int64_t n, int64_t nc, int m);
+void slot_set_params(Slot &s, double eps1, double eps2, double kappa);
+void slot_set_mode(Slot &s, int mode);
+
+// ---------------------------------------------------------------------------
+// A batch: the device array of Mol records and the per-launch block lists.
+struct Batch {
+    std::vector<Slot *> slots;
+    Mol *d_mols = nullptr;
+    int2 *d_elem = nullptr;   int n_elem = 0;   // (mol, block) over ceil(n/256)
+    int2 *d_blas = nullptr;   int n_blas = 0;   // (mol, block) over nb
+    int4 *d_tiles64 = nullptr; int n_tiles64 = 0;  // (mol, row block, split, 0)
+    int4 *d_tiles32 = nullptr; int n_tiles32 = 0;
+    int4 *d_rx = nullptr;     int n_rx = 0;     // (mol, charge block, split, 0)
+    int *d_counter = nullptr;  // tile queue of the persistent product
+    KrylovStatus *d_status = nullptr;  // gathered statuses, one per molecule
+    KrylovStatus *h_status = nullptr;  // their pinned host mirror (in h_pinned)
+    void *h_pinned = nullptr;          // staging for uploads, same layout as d_mem
+    int mode = 0;                      // solve mode shared by the batch
+    void *d_mem = nullptr;
+    int64_t cap_bytes = 0;
+    bool persistent = true;
+    int grid64 = 0, grid32 = 0;  // persistent grid sizes
+    // captured round (hipGraph), valid while the batch is unchanged
+    hipGraphExec_t graph = nullptr;
+    bool graph_valid = false;
+};
+
+int batch_build(Batch &b, hipStream_t stream, std::string &err);
+void batch_free(Batch &b);
 
 }  // namespace gabi
 
+// ---------------------------------------------------------------------------
 struct gabi_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // records graphs only, never executes
     std::string err;
 
-    // surface, N elements
-    int64_t n = 0;
-    double4 *pos = nullptr;   // (cx, cy, cz, area)
-    double4 *nrm = nullptr;   // (nx, ny, nz, 0)
-    float4 *nrm32 = nullptr;  // FP32 normals for the mixed product
-    double4 *wgt = nullptr;   // per-product source weights (s, mx, my, mz)
-    float4 *wgt32 = nullptr;
-    double *part = nullptr;   // pair partial sums [splits][2][n]
-    int64_t part_len = 0;
-    std::vector<double> host_centroids;  // 3n, for validation
-
-    // charges
-    int64_t nc = 0;
-    bool charges_set = false;
-    double4 *chg = nullptr;   // (px, py, pz, q)
-    double *phi_dev = nullptr;   // reaction potential at the charges
-    double *phi_part = nullptr;  // reaction-potential partials
-    int64_t phi_part_len = 0;
-    std::vector<double> host_charges;  // 4nc
-
-    // parameters
-    bool params_set = false;
+    gabi::Slot slot;
+    gabi::Batch batch;
+    bool batch_dirty = true;
+    gabi::Mol uploaded{};  // descriptor the batch was last built from
+    bool geom_dirty = true, chg_dirty = true;
+    int64_t n = 0, nc = 0;
+    int64_t slot_n = -1, slot_nc = -1;
+    int m_alloc = 0;
+    bool charges_set = false, params_set = false, have_solution = false;
     double eps1 = 1.0, eps2 = 80.0, kappa = 0.0;
+    std::vector<double> host_centroids;  // 3n, for validation
+    std::vector<double> host_charges;    // 4nc
+    std::vector<double4> host_pos, host_nrm;
+    std::vector<float4> host_nrm32;
 
-    // vectors of length 2n
-    double *vec_u = nullptr;    // product input / last solution
-    double *vec_y = nullptr;    // product output
-    double *vec_b = nullptr;    // right-hand side
-    double *vec_in = nullptr;   // staging for host-pointer entry points
-    bool have_solution = false;
-
-    // reductions and small device scalars
-    double *red = nullptr;      // [2][kBlasBlocksMax] ping-pong partials
-    double *scalars = nullptr;  // small device scalars (energy, ...)
-
-    // Krylov workspace (allocated on first solve, sized for `kry_m`)
-    int kry_m = 0;
-    double *V = nullptr;        // (m+1) x 2n basis
-    double *H = nullptr;        // (m+1) x m Hessenberg, row-major
-    double *givens = nullptr;   // cs[m], sn[m], g[m+1], hn[m]
-    double *gm_b = nullptr;     // right-hand side of the current GMRES run
-    double *gm_x = nullptr;     // iterate
-    double *gm_r = nullptr;     // residual
-    double *gm_w = nullptr;     // Arnoldi work vector
-    double *ir_x = nullptr;     // refinement iterate
-    double *ir_r = nullptr;     // refinement residual
-    gabi::KrylovStatus *status = nullptr;       // device
-    gabi::KrylovStatus *status_host = nullptr;  // pinned host mirror
-
-    gabi::Timing timing;
-    int64_t bytes = 0;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+    double total_ms[2] = {0, 0};
+    int64_t count[2] = {0, 0};
 };
 
 namespace gabi {
@@ -113,40 +180,35 @@ namespace gabi {
 // ---- errors ---------------------------------------------------------------
 int fail(gabi_ctx *ctx, int code, const std::string &msg);
 int hip_fail(gabi_ctx *ctx, hipError_t e, const char *what);
-#define GABI_HIP(ctx, expr)                                        \
-    do {                                                           \
-        hipError_t e_ = (expr);                                    \
+#define GABI_HIP(ctx, expr)                                            \
+    do {                                                               \
+        hipError_t e_ = (expr);                                        \
         if (e_ != hipSuccess) return ::gabi::hip_fail(ctx, e_, #expr); \
     } while (0)
 
-int dev_alloc(gabi_ctx *ctx, void **p, size_t bytes);
-void dev_free(gabi_ctx *ctx, void **p, size_t bytes);
+// ---- launchers ---------------------------------------------------------------
+enum PrepMode { kPrepCycle0 = 0, kPrepCycleJ = 1, kPrepResX = 2, kPrepU = 3, kPrepSol = 4 };
+enum FinishMode { kFinishDot = 0, kFinishRes = 1, kFinishY = 2 };
 
-// ---- launchers (matvec.hip) -----------------------------------------------
-// Source weights from u (length 2n, device) scaled by 1/(*scale) when scale
-// is non-null; if store is non-null the scaled vector is written there.
-void launch_prep(gabi_ctx *ctx, int precision, const double *u,
-                 const double *scale, double *store, const int32_t *skip);
-// Pair sums into ctx->part.  skip: device flag, non-zero skips the work.
-void launch_pair(gabi_ctx *ctx, int precision, const int32_t *skip);
-// y = diag(u) - sum of partials.
-void launch_finish(gabi_ctx *ctx, int precision, const double *u, double *y);
-// Full product y = A u (u, y device, length 2n).
-int matvec_device(gabi_ctx *ctx, int precision, const double *u, double *y);
+struct Timer {  // optional event pairs around product launches
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *pending[2] = {nullptr, nullptr};
+};
 
-// ---- source terms and energy (sources.hip) --------------------------------
-void launch_rhs(gabi_ctx *ctx, double *b);
-// Reaction potential at the charges from the weights in ctx->wgt; writes
-// nc values to phi (device).  If energy_out is non-null, also writes
-// E_sol in kcal/mol there (device scalar).
-int launch_reaction(gabi_ctx *ctx, double *phi, double *energy_out);
-
-// ---- Krylov (krylov.hip) --------------------------------------------------
-int ensure_krylov(gabi_ctx *ctx, int m);
-int solve_device(gabi_ctx *ctx, const gabi_solve_opts &opts,
-                 const double *x0, double *u, gabi_solve_info *info);
-
-// ---- reductions -----------------------------------------------------------
-int blas_blocks(int64_t n);
+// matvec.hip
+void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);
+void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer *t);
+void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);
+int pair_occupancy_grid(int precision);
+// sources.hip
+void launch_rhs(const Batch &b, hipStream_t s);
+void launch_reaction(const Batch &b, hipStream_t s);
+// krylov.hip
+void enqueue_init(Batch &b, hipStream_t s, bool x0_given, const Timer *t);
+void enqueue_round(Batch &b, hipStream_t s, const Timer *t);
+void enqueue_gather(Batch &b, hipStream_t s);
+void enqueue_finalize(Batch &b, hipStream_t s);
+int run_round(Batch &b, hipStream_t s, hipStream_t capture, const Timer *t,
+              bool use_graph, std::string &err);
+void set_solve_targets(Slot &slot, double tol, double inner_tol, int maxit);
 
 }  // namespace gabi

@@ -1,22 +1,27 @@
 // Restarted GMRES(m) on the device (arXiv:1301.5885, Section 2.2 and
 // Section 2.4: GMRES of Saad and Schultz, x0 = 0, restarted every m steps
 // from the current iterate) and the mixed-precision iterative refinement
-// around it.
+// around it, for a batch of molecules.
 //
 // Arnoldi with modified Gram-Schmidt: for step j, w = A v_j, then for
 // i = 0..j in order h_ij = <w, v_i>, w <- w - h_ij v_i; h_{j+1,j} = ||w||;
 // Givens rotations reduce H to triangular form and carry the residual
-// estimate |g_{j+1}|.  Every MGS substep is one launch: it finishes the
-// previous dot product (each workgroup adds the same fixed-order partials,
-// so all agree bitwise), applies the previous update to its slice of w and
-// emits its partial of the next dot product.  A device flag ends the cycle
-// early (estimate below tol, breakdown, iteration cap); the remaining
-// launches of the cycle see the flag and return at once.  The host reads
-// one small status record per cycle.
+// estimate |g_{j+1}|.  Every MGS substep is one launch over all molecules:
+// each workgroup adds its molecule's fixed-order dot partials (all
+// workgroups of a molecule agree bitwise), applies the previous update to
+// its slice of w and emits its partial of the next dot product.  A per
+// molecule device flag ends its cycle early (estimate below tol, breakdown,
+// iteration cap); the remaining launches skip that molecule.
+//
+// A round is: one cycle of m Arnoldi steps, x += V y, the explicit FP64
+// residual, and the start of the next cycle.  For the FP64 solver the cycle
+// products are FP64 (restarted GMRES exactly as the paper runs it); for the
+// mixed solver they are FP32-pair products while the residual that starts
+// every cycle is FP64 (iterative refinement whose inner solve is one cycle).
+// The host reads one status record per molecule per round.
 //
 // All Krylov vectors, H, the rotations and every reduction are FP64.
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 
 #include "gabi_internal.h"
@@ -24,153 +29,142 @@
 
 namespace gabi {
 
-int blas_blocks(int64_t n) {
-    int64_t b = (n + kBlock - 1) / kBlock;
-    if (b > kBlasBlocksMax) b = kBlasBlocksMax;
-    if (b < 1) b = 1;
-    return (int)b;
+enum CopyMode { kCopyRhsToResOut = 0, kZeroResX = 1, kCopyResXToSol = 2 };
+
+// MODE (compile time): res_out = rhs_dst, res_x = 0, or sol = res_x.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void copy_kernel(const Mol *__restrict__ mols,
+                                                      const int2 *__restrict__ list) {
+    const int2 e = list[blockIdx.x];
+    const Mol &M = mols[e.x];
+    const int i = e.y * kBlock + threadIdx.x;
+    const int n = M.n;
+    if (i >= n) return;
+    double *dst = MODE == kCopyRhsToResOut ? M.res_out : MODE == kZeroResX ? M.res_x : M.sol;
+    if constexpr (MODE == kZeroResX) {
+        dst[i] = 0.0;
+        dst[n + i] = 0.0;
+    } else {
+        const double *src = MODE == kCopyRhsToResOut ? M.rhs_dst : M.res_x;
+        dst[i] = src[i];
+        dst[n + i] = src[n + i];
+    }
 }
 
-// ----------------------------------------------------------------- kernels
-// Partials of <a, b> over the 2n entries; element i covers i and n + i.
-__global__ __launch_bounds__(kBlock) void dot_partial_kernel(
-    int n, const double *__restrict__ a, const double *__restrict__ b,
-    double *__restrict__ red) {
-    __shared__ double lds[kBlock / 64];
-    double s = 0.0;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-        s = __builtin_fma(a[i], b[i], __builtin_fma(a[n + i], b[n + i], s));
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) red[blockIdx.x] = s;
-}
-
-__device__ __forceinline__ double sum_partials(const double *red, int nb,
-                                               double *lds) {
+__device__ __forceinline__ double sum_partials(const double *red, int nb, double *lds) {
     double v = 0.0;
     for (int t = threadIdx.x; t < nb; t += kBlock) v += red[t];
     return block_sum(v, lds);
 }
 
-__global__ __launch_bounds__(kBlock) void run_init_kernel(
-    const double *__restrict__ red, int nb, KrylovStatus *st, double tol,
-    int maxit) {
+// partials of ||rhs||^2
+__global__ __launch_bounds__(kBlock) void dot_rhs_kernel(const Mol *__restrict__ mols,
+                                                         const int2 *__restrict__ list) {
     __shared__ double lds[kBlock / 64];
-    const double bb = sum_partials(red, nb, lds);
+    const int2 e = list[blockIdx.x];
+    const Mol &M = mols[e.x];
+    const int n = M.n;
+    const double *a = M.rhs_dst;
+    double s = 0.0;
+    for (int i = e.y * kBlock + threadIdx.x; i < n; i += M.nb * kBlock)
+        s = __builtin_fma(a[i], a[i], __builtin_fma(a[n + i], a[n + i], s));
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) M.red[e.y] = s;
+}
+
+// one workgroup per molecule: ||b||, targets, counters
+__global__ __launch_bounds__(kBlock) void init_kernel(const Mol *__restrict__ mols) {
+    __shared__ double lds[kBlock / 64];
+    const Mol &M = mols[blockIdx.x];
+    const double bb = sum_partials(M.red, M.nb, lds);
     if (threadIdx.x == 0) {
-        st->beta = sqrt(bb);
-        st->tol = tol;
-        st->maxit = maxit;
+        KrylovStatus *st = M.st;
+        st->beta0 = sqrt(bb);
+        st->beta = st->beta0;
+        st->tol0 = M.tol0;
+        st->tol = M.tol0;
+        st->inner_tol = M.inner_tol;
+        st->maxit = M.maxit;
         st->iters = 0;
         st->k = 0;
         st->done = 0;
-        st->rnorm = st->beta;
-        st->gabs = st->beta;
+        st->converged = 0;
+        st->rnorm = st->beta0;
+        st->gabs = st->beta0;
+        st->energy = 0.0;
     }
 }
 
-// r = b - (D x - sum of pair partials); partials of ||r||^2.
-__global__ __launch_bounds__(kBlock) void finish_residual_kernel(
-    int n, int splits, const double *__restrict__ part,
-    const double *__restrict__ x, const double *__restrict__ b, double d_top,
-    double d_bot, double *__restrict__ r, double *__restrict__ red) {
+// one workgroup per molecule: ||res_out|| from the residual partials, the
+// convergence test, and the start of the next cycle
+__global__ __launch_bounds__(kBlock) void start_kernel(const Mol *__restrict__ mols) {
     __shared__ double lds[kBlock / 64];
-    double s = 0.0;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        double st = 0.0, sb = 0.0;
-        for (int p = 0; p < splits; ++p) {
-            st += part[(size_t)(2 * p) * n + i];
-            sb += part[(size_t)(2 * p + 1) * n + i];
-        }
-        const double rt = b[i] - (d_top * x[i] - st);
-        const double rb = b[n + i] - (d_bot * x[n + i] - sb);
-        r[i] = rt;
-        r[n + i] = rb;
-        s = __builtin_fma(rt, rt, __builtin_fma(rb, rb, s));
+    const Mol &M = mols[blockIdx.x];
+    const double rr = sum_partials(M.red, M.nb, lds);
+    if (threadIdx.x != 0) return;
+    KrylovStatus *st = M.st;
+    const double rn = sqrt(rr);
+    st->rnorm = rn;
+    st->gabs = rn;
+    st->k = 0;
+    const int conv = (st->beta0 == 0.0 || rn == 0.0 || rn / st->beta0 <= st->tol0) ? 1 : 0;
+    st->converged = conv;
+    if (M.mode == kModeMixed && rn > 0.0) {
+        st->beta = rn;
+        st->tol = fmax(st->inner_tol, 0.1 * st->tol0 * st->beta0 / rn);
+    } else {
+        st->beta = st->beta0;
+        st->tol = st->tol0;
     }
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) red[blockIdx.x] = s;
+    for (int i = 0; i <= M.m; ++i) M.g[i] = 0.0;
+    M.g[0] = rn;
+    st->done = (conv || st->iters >= st->maxit) ? 1 : 0;
 }
 
-// Start of a cycle from the explicit residual: ||r||, g = (||r||, 0, ...),
-// and the decision whether another cycle is needed.
-__global__ __launch_bounds__(kBlock) void cycle_start_kernel(
-    const double *__restrict__ red, int nb, KrylovStatus *st,
-    double *__restrict__ g, int m) {
+// MGS substep i of step j (i = j + 1: the closing norm).  h = <w, v_{i-1}>
+// from the partials, w -= h v_{i-1}, partials of <w, v_i> (or of <w, w>).
+__global__ __launch_bounds__(kBlock) void mgs_kernel(const Mol *__restrict__ mols,
+                                                     const int2 *__restrict__ list,
+                                                     int i, int j) {
     __shared__ double lds[kBlock / 64];
-    const double rr = sum_partials(red, nb, lds);
-    if (threadIdx.x == 0) {
-        const double rn = sqrt(rr);
-        st->rnorm = rn;
-        st->gabs = rn;
-        st->k = 0;
-        for (int i = 0; i <= m; ++i) g[i] = 0.0;
-        g[0] = rn;
-        st->done = (st->beta == 0.0 || rn / st->beta <= st->tol ||
-                    st->iters >= st->maxit || rn == 0.0) ? 1 : 0;
-    }
-}
-
-// w = D v - sum of pair partials (w = A v_j); partials of <w, v_0>.
-__global__ __launch_bounds__(kBlock) void finish_dot_kernel(
-    int n, int splits, const double *__restrict__ part,
-    const double *__restrict__ v, double d_top, double d_bot,
-    double *__restrict__ w, const double *__restrict__ v0,
-    double *__restrict__ red, const int32_t *__restrict__ skip) {
-    if (*skip) return;
-    __shared__ double lds[kBlock / 64];
-    double s = 0.0;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        double st = 0.0, sb = 0.0;
-        for (int p = 0; p < splits; ++p) {
-            st += part[(size_t)(2 * p) * n + i];
-            sb += part[(size_t)(2 * p + 1) * n + i];
-        }
-        const double wt = d_top * v[i] - st;
-        const double wb = d_bot * v[n + i] - sb;
-        w[i] = wt;
-        w[n + i] = wb;
-        s = __builtin_fma(wt, v0[i], __builtin_fma(wb, v0[n + i], s));
-    }
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) red[blockIdx.x] = s;
-}
-
-// MGS substep: h = <w, v_prev> from the previous partials, w -= h v_prev,
-// then partials of <w, v_next> (or of <w, w> when v_next is null).
-__global__ __launch_bounds__(kBlock) void mgs_kernel(
-    int n, double *__restrict__ w, const double *__restrict__ v_prev,
-    const double *__restrict__ v_next, const double *__restrict__ red_in,
-    int nb, double *__restrict__ red_out, double *__restrict__ h_out,
-    const int32_t *__restrict__ skip) {
-    if (*skip) return;
-    __shared__ double lds[kBlock / 64];
+    const int2 e = list[blockIdx.x];
+    const Mol &M = mols[e.x];
+    if (M.st->done) return;
+    const int n = M.n, nb = M.nb, m = M.m;
+    const size_t len = 2 * (size_t)n;
+    const double *red_in = M.red + ((i - 1) & 1) * kBlasBlocksMax;
+    double *red_out = M.red + (i & 1) * kBlasBlocksMax;
     const double h = sum_partials(red_in, nb, lds);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *h_out = h;
+    if (e.y == 0 && threadIdx.x == 0) M.H[(i - 1) * m + j] = h;
+    const double *vp = M.V + (size_t)(i - 1) * len;
+    const double *vn = i <= j ? M.V + (size_t)i * len : nullptr;
+    double *w = M.w;
     double s = 0.0;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const double wt = __builtin_fma(-h, v_prev[i], w[i]);
-        const double wb = __builtin_fma(-h, v_prev[n + i], w[n + i]);
-        w[i] = wt;
-        w[n + i] = wb;
-        if (v_next)
-            s = __builtin_fma(wt, v_next[i], __builtin_fma(wb, v_next[n + i], s));
+    for (int t = e.y * kBlock + threadIdx.x; t < n; t += nb * kBlock) {
+        const double wt = __builtin_fma(-h, vp[t], w[t]);
+        const double wb = __builtin_fma(-h, vp[n + t], w[n + t]);
+        w[t] = wt;
+        w[n + t] = wb;
+        if (vn)
+            s = __builtin_fma(wt, vn[t], __builtin_fma(wb, vn[n + t], s));
         else
             s = __builtin_fma(wt, wt, __builtin_fma(wb, wb, s));
     }
     s = block_sum(s, lds);
-    if (threadIdx.x == 0) red_out[blockIdx.x] = s;
+    if (threadIdx.x == 0) red_out[e.y] = s;
 }
 
-// h_{j+1,j} = ||w||, rotations, residual estimate, stopping decision.
-__global__ __launch_bounds__(kBlock) void givens_kernel(
-    int j, int m, const double *__restrict__ red, int nb,
-    double *__restrict__ H, double *__restrict__ cs, double *__restrict__ sn,
-    double *__restrict__ g, double *__restrict__ hn_out, KrylovStatus *st) {
-    if (st->done) return;
+// one workgroup per molecule: h_{j+1,j} = ||w||, rotations, estimate, stop
+__global__ __launch_bounds__(kBlock) void givens_kernel(const Mol *__restrict__ mols, int j) {
     __shared__ double lds[kBlock / 64];
-    const double hn = sqrt(sum_partials(red, nb, lds));
+    const Mol &M = mols[blockIdx.x];
+    KrylovStatus *st = M.st;
+    if (st->done) return;
+    const int m = M.m;
+    const double hn = sqrt(sum_partials(M.red + ((j + 1) & 1) * kBlasBlocksMax, M.nb, lds));
     if (threadIdx.x != 0) return;
-    hn_out[j] = hn;
+    double *H = M.H, *cs = M.cs, *sn = M.sn, *g = M.g;
+    M.hn[j] = hn;
     H[(j + 1) * m + j] = hn;
     for (int i = 0; i < j; ++i) {
         const double a = H[i * m + j], c = H[(i + 1) * m + j];
@@ -192,344 +186,137 @@ __global__ __launch_bounds__(kBlock) void givens_kernel(
         st->done = 1;
 }
 
-// x += V y with H(0:k,0:k) y = g(0:k); each workgroup solves the small
-// triangular system itself (identical arithmetic in every workgroup).
-__global__ __launch_bounds__(kBlock) void update_x_kernel(
-    int n, int m, const double *__restrict__ V, const double *__restrict__ H,
-    const double *__restrict__ g, const KrylovStatus *st, double *__restrict__ x) {
-    __shared__ double y[64];
-    const int k = st->k;
+// upd_dst += V y with H(0:k,0:k) y = g(0:k); every workgroup solves the small
+// triangular system itself (identical arithmetic in all of them).
+__global__ __launch_bounds__(kBlock) void update_kernel(const Mol *__restrict__ mols,
+                                                        const int2 *__restrict__ list) {
+    __shared__ double y[kMaxRestart];
+    const int2 e = list[blockIdx.x];
+    const Mol &M = mols[e.x];
+    const int k = M.st->k;
+    if (k == 0) return;
+    const int m = M.m, n = M.n;
     if (threadIdx.x == 0) {
         for (int i = k - 1; i >= 0; --i) {
-            double s = g[i];
-            for (int t = i + 1; t < k; ++t) s -= H[i * m + t] * y[t];
-            y[i] = s / H[i * m + i];
+            double s = M.g[i];
+            for (int t = i + 1; t < k; ++t) s -= M.H[i * m + t] * y[t];
+            y[i] = s / M.H[i * m + i];
         }
     }
     __syncthreads();
     const size_t len = 2 * (size_t)n;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    double *x = M.upd_dst;
+    for (int i = e.y * kBlock + threadIdx.x; i < n; i += M.nb * kBlock) {
         double xt = x[i], xb = x[n + i];
         for (int c = 0; c < k; ++c) {
-            xt = __builtin_fma(y[c], V[c * len + i], xt);
-            xb = __builtin_fma(y[c], V[c * len + n + i], xb);
+            xt = __builtin_fma(y[c], M.V[c * len + i], xt);
+            xb = __builtin_fma(y[c], M.V[c * len + n + i], xb);
         }
         x[i] = xt;
         x[n + i] = xb;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void fill_kernel(int64_t len, double *p,
-                                                      double v) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < len;
-         i += (int64_t)gridDim.x * kBlock)
-        p[i] = v;
+__global__ void gather_status_kernel(const Mol *__restrict__ mols, int nmol,
+                                     KrylovStatus *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nmol) out[k] = *mols[k].st;
 }
 
-__global__ __launch_bounds__(kBlock) void axpy_kernel(int64_t len, double a,
-                                                      const double *x,
-                                                      double *y) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < len;
-         i += (int64_t)gridDim.x * kBlock)
-        y[i] = __builtin_fma(a, x[i], y[i]);
+// ---------------------------------------------------------------- host
+static void launch_copy(const Batch &b, hipStream_t s, int mode) {
+    const dim3 g(b.n_elem), blk(kBlock);
+    if (mode == kCopyRhsToResOut)
+        hipLaunchKernelGGL(copy_kernel<kCopyRhsToResOut>, g, blk, 0, s, b.d_mols, b.d_elem);
+    else if (mode == kZeroResX)
+        hipLaunchKernelGGL(copy_kernel<kZeroResX>, g, blk, 0, s, b.d_mols, b.d_elem);
+    else
+        hipLaunchKernelGGL(copy_kernel<kCopyResXToSol>, g, blk, 0, s, b.d_mols, b.d_elem);
 }
 
-// ----------------------------------------------------------------- host
-static void fill(gabi_ctx *ctx, double *p, int64_t len, double v) {
-    int64_t blocks = (len + kBlock - 1) / kBlock;
-    if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(fill_kernel, dim3((int)blocks), dim3(kBlock), 0,
-                       ctx->stream, len, p, v);
-}
+static int nmol(const Batch &b) { return (int)b.slots.size(); }
 
-static void axpy(gabi_ctx *ctx, double a, const double *x, double *y, int64_t len) {
-    int64_t blocks = (len + kBlock - 1) / kBlock;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(axpy_kernel, dim3((int)blocks), dim3(kBlock), 0,
-                       ctx->stream, len, a, x, y);
-}
-
-int ensure_krylov(gabi_ctx *ctx, int m) {
-    if (ctx->kry_m == m && ctx->V) return GABI_OK;
-    const int64_t len = 2 * ctx->n;
-    if (ctx->V) {
-        dev_free(ctx, (void **)&ctx->V, sizeof(double) * len * (ctx->kry_m + 1));
-        dev_free(ctx, (void **)&ctx->H, sizeof(double) * (ctx->kry_m + 1) * ctx->kry_m);
-        dev_free(ctx, (void **)&ctx->givens, sizeof(double) * (4 * ctx->kry_m + 1));
-        ctx->kry_m = 0;
-    }
-    int rc;
-    if ((rc = dev_alloc(ctx, (void **)&ctx->V, sizeof(double) * len * (m + 1)))) return rc;
-    if ((rc = dev_alloc(ctx, (void **)&ctx->H, sizeof(double) * (m + 1) * m))) return rc;
-    if ((rc = dev_alloc(ctx, (void **)&ctx->givens, sizeof(double) * (4 * m + 1)))) return rc;
-    ctx->kry_m = m;
-    if (!ctx->gm_b) {
-        double **vs[] = {&ctx->gm_b, &ctx->gm_x, &ctx->gm_r, &ctx->gm_w,
-                         &ctx->ir_x, &ctx->ir_r};
-        for (double **p : vs)
-            if ((rc = dev_alloc(ctx, (void **)p, sizeof(double) * len))) return rc;
-    }
-    if (!ctx->status) {
-        if ((rc = dev_alloc(ctx, (void **)&ctx->status, sizeof(KrylovStatus)))) return rc;
-        GABI_HIP(ctx, hipHostMalloc((void **)&ctx->status_host, sizeof(KrylovStatus),
-                                    hipHostMallocDefault));
-    }
-    return GABI_OK;
-}
-
-static int read_status(gabi_ctx *ctx) {
-    GABI_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(KrylovStatus),
-                                 hipMemcpyDeviceToHost, ctx->stream));
-    GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return GABI_OK;
-}
-
-struct RunResult {
-    int64_t iterations = 0, matvecs = 0, restarts = 0;
-    double rel_residual = 0.0;
-    bool converged = false;
-};
-
-// Launch sequence of one restarted-GMRES run on A_prec (see gmres_run).
-struct Run {
-    gabi_ctx *ctx;
-    int prec, m, n, nb;
-    PairLaunch L;
-    double d_top, d_bot;
-    double *red0, *red1, *cs, *sn, *g, *hn;
-    KrylovStatus *st;
-
-    Run(gabi_ctx *c, int precision, int m_) : ctx(c), prec(precision), m(m_) {
-        n = (int)ctx->n;
-        nb = blas_blocks(n);
-        L = pair_launch(n, prec);
-        const double eps = ctx->eps2 / ctx->eps1;
-        d_top = 0.5 * (1.0 + eps);
-        d_bot = 0.5 * (1.0 + 1.0 / eps);
-        red0 = ctx->red;
-        red1 = ctx->red + kBlasBlocksMax;
-        cs = ctx->givens;
-        sn = cs + m;
-        g = sn + m;
-        hn = g + m + 1;
-        st = ctx->status;
-    }
-
-    // m Arnoldi steps from v_0 = gm_r / ||gm_r||, then x += V y.
-    void arnoldi_cycle() {
-        const int64_t len = 2 * (int64_t)n;
-        const int32_t *done = &st->done;
-        const dim3 bg(nb), bb(kBlock);
-        for (int j = 0; j < m; ++j) {
-            double *vj = ctx->V + (size_t)j * len;
-            if (j == 0)
-                launch_prep(ctx, prec, ctx->gm_r, &st->rnorm, vj, done);
-            else
-                launch_prep(ctx, prec, ctx->gm_w, hn + (j - 1), vj, done);
-            launch_pair(ctx, prec, done);
-            hipLaunchKernelGGL(finish_dot_kernel, bg, bb, 0, ctx->stream, n,
-                               L.splits, ctx->part, vj, d_top, d_bot,
-                               ctx->gm_w, ctx->V, red0, done);
-            for (int i = 1; i <= j; ++i) {
-                const double *rin = (i - 1) & 1 ? red1 : red0;
-                double *rout = i & 1 ? red1 : red0;
-                hipLaunchKernelGGL(mgs_kernel, bg, bb, 0, ctx->stream, n,
-                                   ctx->gm_w, ctx->V + (size_t)(i - 1) * len,
-                                   ctx->V + (size_t)i * len, rin, nb, rout,
-                                   ctx->H + (size_t)(i - 1) * m + j, done);
-            }
-            const double *rin = j & 1 ? red1 : red0;
-            double *rout = (j + 1) & 1 ? red1 : red0;
-            hipLaunchKernelGGL(mgs_kernel, bg, bb, 0, ctx->stream, n, ctx->gm_w,
-                               vj, (const double *)nullptr, rin, nb, rout,
-                               ctx->H + (size_t)j * m + j, done);
-            hipLaunchKernelGGL(givens_kernel, dim3(1), bb, 0, ctx->stream, j, m,
-                               rout, nb, ctx->H, cs, sn, g, hn, st);
-        }
-        hipLaunchKernelGGL(update_x_kernel, bg, bb, 0, ctx->stream, n, m,
-                           ctx->V, ctx->H, g, st, ctx->gm_x);
-    }
-
-    // gm_r = gm_b - A gm_x and the start of the next cycle.
-    void residual_and_restart() {
-        launch_prep(ctx, prec, ctx->gm_x, nullptr, nullptr, nullptr);
-        launch_pair(ctx, prec, nullptr);
-        hipLaunchKernelGGL(finish_residual_kernel, dim3(nb), dim3(kBlock), 0,
-                           ctx->stream, n, L.splits, ctx->part, ctx->gm_x,
-                           ctx->gm_b, d_top, d_bot, ctx->gm_r, red0);
-        hipLaunchKernelGGL(cycle_start_kernel, dim3(1), dim3(kBlock), 0,
-                           ctx->stream, red0, nb, st, g, m);
-    }
-};
-
-// Restarted GMRES(m) on A_prec x = gm_b with the iterate in gm_x (x_zero:
-// gm_x holds zeros) and relative tolerance tol on the explicit residual of
-// the same operator.  single_cycle: exactly one cycle from x = 0 and no
-// closing residual (the refinement loop forms that in FP64 instead).
-static int gmres_run(gabi_ctx *ctx, int prec, bool x_zero, double tol,
-                     int maxit, int m, RunResult *res, bool single_cycle) {
-    Run run(ctx, prec, m);
-    const int64_t len = 2 * (int64_t)run.n;
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(run.nb), dim3(kBlock), 0,
-                       ctx->stream, run.n, ctx->gm_b, ctx->gm_b, run.red0);
-    hipLaunchKernelGGL(run_init_kernel, dim3(1), dim3(kBlock), 0, ctx->stream,
-                       run.red0, run.nb, run.st, tol, maxit);
-    if (x_zero) {
-        GABI_HIP(ctx, hipMemcpyAsync(ctx->gm_r, ctx->gm_b, sizeof(double) * len,
-                                     hipMemcpyDeviceToDevice, ctx->stream));
-        hipLaunchKernelGGL(cycle_start_kernel, dim3(1), dim3(kBlock), 0,
-                           ctx->stream, run.red0, run.nb, run.st, run.g, m);
+void enqueue_init(Batch &b, hipStream_t s, bool x0_given, const Timer *t) {
+    launch_rhs(b, s);
+    hipLaunchKernelGGL(dot_rhs_kernel, dim3(b.n_blas), dim3(kBlock), 0, s, b.d_mols, b.d_blas);
+    hipLaunchKernelGGL(init_kernel, dim3(nmol(b)), dim3(kBlock), 0, s, b.d_mols);
+    if (x0_given) {
+        launch_prep(b, s, GABI_FP64, kPrepResX, 0, false);
+        launch_pair(b, s, GABI_FP64, false, t);
+        launch_finish(b, s, GABI_FP64, kFinishRes, 0, false);
     } else {
-        run.residual_and_restart();
-        res->matvecs++;
+        launch_copy(b, s, kZeroResX);
+        launch_copy(b, s, kCopyRhsToResOut);
     }
-    GABI_HIP(ctx, hipGetLastError());
-    int rc;
-    if (single_cycle) {
-        run.arnoldi_cycle();
-        GABI_HIP(ctx, hipGetLastError());
-        if ((rc = read_status(ctx))) return rc;
-        const KrylovStatus &h = *ctx->status_host;
-        res->restarts = 1;
-        res->iterations = h.iters;
-        res->matvecs += h.iters;
-        res->rel_residual = h.beta > 0 ? h.gabs / h.beta : 0.0;
-        res->converged = res->rel_residual <= tol;
-        return GABI_OK;
-    }
-    if ((rc = read_status(ctx))) return rc;
-    for (;;) {
-        const KrylovStatus &h = *ctx->status_host;
-        res->rel_residual = h.beta > 0 ? h.rnorm / h.beta : 0.0;
-        if (h.beta == 0.0) {
-            fill(ctx, ctx->gm_x, len, 0.0);
-            res->converged = true;
-            break;
-        }
-        if (h.rnorm / h.beta <= tol || h.rnorm == 0.0) {
-            res->converged = true;
-            break;
-        }
-        if (h.iters >= maxit) break;
-        run.arnoldi_cycle();
-        run.residual_and_restart();
-        GABI_HIP(ctx, hipGetLastError());
-        if ((rc = read_status(ctx))) return rc;
-        res->restarts++;
-    }
-    res->iterations = ctx->status_host->iters;
-    res->matvecs += res->iterations + res->restarts;
-    return GABI_OK;
+    hipLaunchKernelGGL(start_kernel, dim3(nmol(b)), dim3(kBlock), 0, s, b.d_mols);
 }
 
-int solve_device(gabi_ctx *ctx, const gabi_solve_opts &opts, const double *x0,
-                 double *u, gabi_solve_info *info) {
-    const auto t0 = std::chrono::steady_clock::now();
-    const int64_t len = 2 * ctx->n;
-    const int m = opts.restart;
-    int rc = ensure_krylov(ctx, m);
-    if (rc) return rc;
-    gabi_solve_info out{};
-
-    launch_rhs(ctx, ctx->vec_b);
-    if (opts.mode == GABI_SOLVE_FP64) {
-        GABI_HIP(ctx, hipMemcpyAsync(ctx->gm_b, ctx->vec_b, sizeof(double) * len,
-                                     hipMemcpyDeviceToDevice, ctx->stream));
-        if (x0)
-            GABI_HIP(ctx, hipMemcpyAsync(ctx->gm_x, x0, sizeof(double) * len,
-                                         hipMemcpyDeviceToDevice, ctx->stream));
-        else
-            fill(ctx, ctx->gm_x, len, 0.0);
-        RunResult r;
-        if ((rc = gmres_run(ctx, GABI_FP64, x0 == nullptr, opts.tol, opts.maxit,
-                            m, &r, false)))
-            return rc;
-        out.iterations = r.iterations;
-        out.matvecs_fp64 = r.matvecs;
-        out.restarts = r.restarts;
-        out.rel_residual = r.rel_residual;
-        out.converged = r.converged;
-        GABI_HIP(ctx, hipMemcpyAsync(ctx->vec_u, ctx->gm_x, sizeof(double) * len,
-                                     hipMemcpyDeviceToDevice, ctx->stream));
-    } else {
-        // FP64 iterative refinement: r = b - A64 x; A32 d = r; x += d.
-        const int n = (int)ctx->n;
-        const int nb = blas_blocks(n);
-        const PairLaunch L = pair_launch(n, GABI_FP64);
-        const double eps = ctx->eps2 / ctx->eps1;
-        const double d_top = 0.5 * (1.0 + eps), d_bot = 0.5 * (1.0 + 1.0 / eps);
-        double *red0 = ctx->red;
-        double beta = 0.0, rnorm = 0.0;
-        // ||b|| via the status record
-        hipLaunchKernelGGL(dot_partial_kernel, dim3(nb), dim3(kBlock), 0,
-                           ctx->stream, n, ctx->vec_b, ctx->vec_b, red0);
-        hipLaunchKernelGGL(run_init_kernel, dim3(1), dim3(kBlock), 0,
-                           ctx->stream, red0, nb, ctx->status, opts.tol, 0);
-        if ((rc = read_status(ctx))) return rc;
-        beta = ctx->status_host->beta;
-        if (x0 && beta > 0.0) {
-            GABI_HIP(ctx, hipMemcpyAsync(ctx->ir_x, x0, sizeof(double) * len,
-                                         hipMemcpyDeviceToDevice, ctx->stream));
-        } else {
-            fill(ctx, ctx->ir_x, len, 0.0);  // b = 0 has the solution u = 0
-        }
-        auto residual = [&](bool zero_x) -> int {
-            if (zero_x) {
-                GABI_HIP(ctx, hipMemcpyAsync(ctx->ir_r, ctx->vec_b, sizeof(double) * len,
-                                             hipMemcpyDeviceToDevice, ctx->stream));
-                rnorm = beta;
-                return GABI_OK;
-            }
-            launch_prep(ctx, GABI_FP64, ctx->ir_x, nullptr, nullptr, nullptr);
-            launch_pair(ctx, GABI_FP64, nullptr);
-            hipLaunchKernelGGL(finish_residual_kernel, dim3(nb), dim3(kBlock), 0,
-                               ctx->stream, n, L.splits, ctx->part, ctx->ir_x,
-                               ctx->vec_b, d_top, d_bot, ctx->ir_r, red0);
-            hipLaunchKernelGGL(run_init_kernel, dim3(1), dim3(kBlock), 0,
-                               ctx->stream, red0, nb, ctx->status, opts.tol, 0);
-            int e = read_status(ctx);
-            if (e) return e;
-            rnorm = ctx->status_host->beta;
-            out.matvecs_fp64++;
-            return GABI_OK;
-        };
-        if ((rc = residual(x0 == nullptr || beta == 0.0))) return rc;
-        out.rel_residual = beta > 0 ? rnorm / beta : 0.0;
-        while (beta > 0 && rnorm / beta > opts.tol && out.outer < opts.max_outer &&
-               out.iterations < opts.maxit) {
-            // one GMRES(m) cycle on the FP32-pair operator from d = 0 with
-            // right-hand side r; it may stop early once its estimate is
-            // below inner_tol ||r|| or a tenth of the final target.
-            GABI_HIP(ctx, hipMemcpyAsync(ctx->gm_b, ctx->ir_r, sizeof(double) * len,
-                                         hipMemcpyDeviceToDevice, ctx->stream));
-            fill(ctx, ctx->gm_x, len, 0.0);
-            const double inner = std::max(opts.inner_tol, 0.1 * opts.tol * beta / rnorm);
-            const int left = (int)std::min<int64_t>(m, opts.maxit - out.iterations);
-            RunResult r;
-            if ((rc = gmres_run(ctx, GABI_FP32_PAIR, true, inner, left, m, &r, true)))
-                return rc;
-            out.iterations += r.iterations;
-            out.matvecs_fp32 += r.matvecs;
-            out.restarts += r.restarts;
-            axpy(ctx, 1.0, ctx->gm_x, ctx->ir_x, len);
-            out.outer++;
-            if ((rc = residual(false))) return rc;
-            out.rel_residual = rnorm / beta;
-            if (r.iterations == 0) break;  // no progress possible
-        }
-        out.converged = beta == 0.0 || rnorm / beta <= opts.tol;
-        GABI_HIP(ctx, hipMemcpyAsync(ctx->vec_u, ctx->ir_x, sizeof(double) * len,
-                                     hipMemcpyDeviceToDevice, ctx->stream));
+void enqueue_round(Batch &b, hipStream_t s, const Timer *t) {
+    const int prec = b.mode == kModeMixed ? GABI_FP32_PAIR : GABI_FP64;
+    const int m = b.slots.empty() ? 0 : b.slots[0]->mol.m;
+    for (int j = 0; j < m; ++j) {
+        launch_prep(b, s, prec, j == 0 ? kPrepCycle0 : kPrepCycleJ, j, true);
+        launch_pair(b, s, prec, true, t);
+        launch_finish(b, s, prec, kFinishDot, j, true);
+        for (int i = 1; i <= j + 1; ++i)
+            hipLaunchKernelGGL(mgs_kernel, dim3(b.n_blas), dim3(kBlock), 0, s, b.d_mols,
+                               b.d_blas, i, j);
+        hipLaunchKernelGGL(givens_kernel, dim3(nmol(b)), dim3(kBlock), 0, s, b.d_mols, j);
     }
-    if (u && u != ctx->vec_u)
-        GABI_HIP(ctx, hipMemcpyAsync(u, ctx->vec_u, sizeof(double) * len,
-                                     hipMemcpyDefault, ctx->stream));
-    GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->have_solution = true;
-    out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (info) *info = out;
-    return out.converged ? GABI_OK : GABI_NOT_CONVERGED;
+    hipLaunchKernelGGL(update_kernel, dim3(b.n_blas), dim3(kBlock), 0, s, b.d_mols, b.d_blas);
+    launch_prep(b, s, GABI_FP64, kPrepResX, 0, false);
+    launch_pair(b, s, GABI_FP64, false, t);
+    launch_finish(b, s, GABI_FP64, kFinishRes, 0, false);
+    hipLaunchKernelGGL(start_kernel, dim3(nmol(b)), dim3(kBlock), 0, s, b.d_mols);
+}
+
+void enqueue_gather(Batch &b, hipStream_t s) {
+    const int nm = nmol(b);
+    hipLaunchKernelGGL(gather_status_kernel, dim3((nm + 63) / 64), dim3(64), 0, s,
+                       b.d_mols, nm, b.d_status);
+    (void)hipMemcpyAsync(b.h_status, b.d_status, sizeof(KrylovStatus) * nm,
+                         hipMemcpyDeviceToHost, s);
+}
+
+void enqueue_finalize(Batch &b, hipStream_t s) {
+    launch_copy(b, s, kCopyResXToSol);
+    launch_prep(b, s, GABI_FP64, kPrepSol, 0, false);
+    launch_reaction(b, s);
+}
+
+// One round, eager or as a replay of the captured graph of this batch.
+int run_round(Batch &b, hipStream_t s, hipStream_t capture, const Timer *t,
+              bool use_graph, std::string &err) {
+    if (use_graph && !t && capture) {
+        if (!b.graph_valid) {
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                enqueue_round(b, capture, nullptr);
+                e = hipStreamEndCapture(capture, &g);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                err = std::string("graph capture of a round failed: ") + hipGetErrorString(e);
+                return GABI_EDEVICE;
+            }
+            b.graph_valid = true;
+        }
+        hipError_t e = hipGraphLaunch(b.graph, s);
+        if (e != hipSuccess) {
+            err = std::string("graph launch failed: ") + hipGetErrorString(e);
+            return GABI_EDEVICE;
+        }
+    } else {
+        enqueue_round(b, s, t);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        err = std::string("round launch failed: ") + hipGetErrorString(e);
+        return GABI_EDEVICE;
+    }
+    return GABI_OK;
 }
 
 }  // namespace gabi

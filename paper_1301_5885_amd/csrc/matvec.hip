@@ -1,91 +1,83 @@
 // The discrete boundary-integral product y = A u of arXiv:1301.5885,
-// Section 2.2, eqs. (eqdbef1)/(eqdbef2), on gfx950.
+// Section 2.2, eqs. (eqdbef1)/(eqdbef2), on gfx950, for a batch of molecules.
 //
 //   y_i     = (1+eps)/2 phi_i   - sum_{j != i} W_j [K1 psi_j + K2 phi_j]
 //   y_{N+i} = (1+1/eps)/2 psi_i - sum_{j != i} W_j [K3 psi_j + K4 phi_j]
 //
 // Three launches per product:
-//   prep    O(N): source weights s_j = W_j psi_j/(4 pi) and
-//           m_j = W_j phi_j nu_j/(4 pi) (FP64, or FP32 for the mixed path);
-//   pair    O(N^2): each thread holds R target rows in registers; a
-//           workgroup streams one split of the sources through LDS in
-//           tiles of 256 (coalesced 32-byte records, broadcast reads), and
-//           writes its two row sums per target to a partial buffer;
-//   finish  O(N S): adds the S split partials in split order and applies
-//           the diagonal.
-// The split count S depends only on N and the precision, so a product's
-// summation order is fixed (bitwise reproducible).  The self term j = i is
-// skipped exactly: only the tiles that overlap the workgroup's own rows run
-// the masked loop.
+//   prep    O(N): source weights s_j = W_j psi_j/(4 pi), m_j = W_j phi_j
+//           nu_j/(4 pi) (FP64, or FP32 for the mixed product);
+//   pair    O(N^2): a tile = (molecule, row block, source split).  Each
+//           thread holds R target rows in registers; the workgroup streams
+//           the split's sources through LDS, 256 records per stage
+//           (coalesced loads, broadcast reads), and writes its two row sums
+//           per target to the molecule's partial buffer.  Tiles of every
+//           molecule in the batch are listed longest first; the persistent
+//           form runs a fixed grid whose workgroups take tiles from an
+//           atomic counter until the list is exhausted, the flat form
+//           launches one workgroup per tile;
+//   finish  O(N S): adds the split partials in split order, applies the
+//           diagonal, and (inside GMRES) emits the first MGS dot partial.
+// The split count depends only on N and the precision, so a molecule's
+// summation order is the same alone or in any batch (bitwise reproducible).
+// The self term j = i is skipped exactly: only the source stages that overlap
+// the tile's own rows run the masked loop.
 #include "gabi_internal.h"
 #include "pair_math.h"
+#include "reduce.h"
 
 namespace gabi {
 
-// ------------------------------------------------------------------ config
-PairLaunch pair_launch(int64_t n, int precision) {
-    PairLaunch L;
-    L.rows_per_thread = (n >= 8192) ? 2 : 1;
-    const int64_t rows_per_block = (int64_t)kBlock * L.rows_per_thread;
-    L.row_blocks = (int)((n + rows_per_block - 1) / rows_per_block);
-    const int64_t tiles = (n + kTile - 1) / kTile;
-    const int64_t target_blocks = 2048;  // about 8 workgroups per CU
-    int64_t want_splits = (target_blocks + L.row_blocks - 1) / L.row_blocks;
-    if (want_splits < 1) want_splits = 1;
-    int64_t tps = (tiles + want_splits - 1) / want_splits;
-    if (tps < 1) tps = 1;
-    L.tiles_per_split = (int)tps;
-    L.splits = (int)((tiles + tps - 1) / tps);
-    (void)precision;
-    return L;
-}
-
 // ------------------------------------------------------------------ prep
+// MODE (compile time) selects the input vector: the cycle start r/||r||
+// (stored as V_0), the Arnoldi vector w/h_{j,j-1} (stored as V_j), the
+// residual iterate, the product input u, or the kept solution.
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void prep_kernel(
-    int n, const double4 *__restrict__ pos, const double4 *__restrict__ nrm,
-    const double *__restrict__ u, const double *__restrict__ scale,
-    double *__restrict__ store, double4 *__restrict__ w64,
-    float4 *__restrict__ w32, const int32_t *__restrict__ skip) {
-    if (skip && *skip) return;
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    double phi = u[j], psi = u[n + j];
-    if (scale) {
-        const double h = *scale;
+    const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision,
+    int j, int skip) {
+    const int2 e = list[blockIdx.x];
+    const Mol &M = mols[e.x];
+    if (skip && M.st->done) return;
+    const int i = e.y * kBlock + threadIdx.x;
+    const int n = M.n;
+    if (i >= n) return;
+    const double *src = MODE == kPrepCycle0 ? M.cyc_src
+                      : MODE == kPrepCycleJ ? M.w
+                      : MODE == kPrepResX   ? M.res_x
+                      : MODE == kPrepSol    ? M.sol
+                                            : M.u;
+    double phi = src[i], psi = src[n + i];
+    if constexpr (MODE == kPrepCycle0 || MODE == kPrepCycleJ) {
+        const double h = MODE == kPrepCycle0 ? M.st->rnorm : M.hn[j - 1];
+        double *store = M.V + (size_t)(MODE == kPrepCycle0 ? 0 : j) * 2 * n;
         phi = phi / h;
         psi = psi / h;
+        store[i] = phi;
+        store[n + i] = psi;
     }
-    if (store) {
-        store[j] = phi;
-        store[n + j] = psi;
-    }
-    const double4 p = pos[j];
-    const double4 nu = nrm[j];
+    const double4 p = M.pos[i];
+    const double4 nu = M.nrm[i];
     const double c = p.w * (1.0 / (4.0 * kPi));
     const double s = c * psi;
     const double t = c * phi;
-    if (w64) w64[j] = make_double4(s, t * nu.x, t * nu.y, t * nu.z);
-    if (w32)
-        w32[j] = make_float4((float)s, (float)(t * nu.x), (float)(t * nu.y),
-                             (float)(t * nu.z));
+    if (precision == GABI_FP64)
+        M.wgt[i] = make_double4(s, t * nu.x, t * nu.y, t * nu.z);
+    else
+        M.wgt32[i] = make_float4((float)s, (float)(t * nu.x), (float)(t * nu.y),
+                                 (float)(t * nu.z));
 }
 
 // ------------------------------------------------------------------ pair
 template <int R, bool MIXED>
-__global__ __launch_bounds__(kBlock) void pair_kernel(
-    int n, int tiles_per_split, const double4 *__restrict__ pos,
-    const double4 *__restrict__ nrm, const float4 *__restrict__ nrm32,
-    const double4 *__restrict__ w64, const float4 *__restrict__ w32,
-    PairConstF64 c64, PairConstF32 c32, double *__restrict__ part,
-    const int32_t *__restrict__ skip) {
-    if (skip && *skip) return;
-    __shared__ double4 s_pos[kTile];
-    __shared__ double4 s_w64[MIXED ? 1 : kTile];
-    __shared__ float4 s_w32[MIXED ? kTile : 1];
-
+__device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
+                                          double4 *s_pos, double4 *s_w64,
+                                          float4 *s_w32) {
+    const int n = M.n;
     const int tid = threadIdx.x;
-    const int row0 = blockIdx.x * kBlock * R;
+    const int row0 = rb * kBlock * R;
     const int row_end = min(n, row0 + kBlock * R);
+    const int tps = MIXED ? M.tps32 : M.tps64;
 
     double tx[R], ty[R], tz[R];
     double tnx[R], tny[R], tnz[R];
@@ -97,17 +89,17 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(
         const int i = row0 + r * kBlock + tid;
         ti[r] = i;
         const int ic = min(i, n - 1);
-        const double4 p = pos[ic];
+        const double4 p = M.pos[ic];
         tx[r] = p.x;
         ty[r] = p.y;
         tz[r] = p.z;
         if constexpr (MIXED) {
-            const float4 q = nrm32[ic];
+            const float4 q = M.nrm32[ic];
             fnx[r] = q.x;
             fny[r] = q.y;
             fnz[r] = q.z;
         } else {
-            const double4 q = nrm[ic];
+            const double4 q = M.nrm[ic];
             tnx[r] = q.x;
             tny[r] = q.y;
             tnz[r] = q.z;
@@ -115,19 +107,21 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(
         top[r] = 0.0;
         bot[r] = 0.0;
     }
+    const PairConstF64 c64{M.kappa, M.eps, M.inv_eps};
+    const PairConstF32 c32{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
 
-    const int j_begin = blockIdx.y * tiles_per_split * kTile;
-    for (int tile = 0; tile < tiles_per_split; ++tile) {
+    const int j_begin = sp * tps * kTile;
+    for (int tile = 0; tile < tps; ++tile) {
         const int jt = j_begin + tile * kTile;
         if (jt >= n) break;
         const int cnt = min(kTile, n - jt);
         __syncthreads();
         if (tid < cnt) {
-            s_pos[tid] = pos[jt + tid];
+            s_pos[tid] = M.pos[jt + tid];
             if constexpr (MIXED)
-                s_w32[tid] = w32[jt + tid];
+                s_w32[tid] = M.wgt32[jt + tid];
             else
-                s_w64[tid] = w64[jt + tid];
+                s_w64[tid] = M.wgt[jt + tid];
         }
         __syncthreads();
         const bool diag = (jt < row_end) && (jt + cnt > row0);
@@ -189,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(
             }
         }
     }
-    double *pt = part + (size_t)(2 * blockIdx.y) * n;
+    double *pt = M.part + (size_t)(2 * sp) * n;
     double *pb = pt + n;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -200,83 +194,168 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(
     }
 }
 
-// ------------------------------------------------------------------ finish
-__global__ __launch_bounds__(kBlock) void finish_kernel(
-    int n, int splits, const double *__restrict__ part,
-    const double *__restrict__ u, double d_top, double d_bot,
-    double *__restrict__ y) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    double st = 0.0, sb = 0.0;
-    for (int s = 0; s < splits; ++s) {
-        st += part[(size_t)(2 * s) * n + i];
-        sb += part[(size_t)(2 * s + 1) * n + i];
+// One workgroup per tile (flat) or a fixed grid draining the tile queue
+// (persistent).  The loop exits for every workgroup once the counter passes
+// the end of the list.
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void pair_kernel(
+    const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
+    int *__restrict__ counter, int persistent, int skip) {
+    __shared__ double4 s_pos[kTile];
+    __shared__ double4 s_w64[MIXED ? 1 : kTile];
+    __shared__ float4 s_w32[MIXED ? kTile : 1];
+    __shared__ int s_next;
+    int t = blockIdx.x;
+    for (;;) {
+        if (persistent) {
+            __syncthreads();
+            if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+            __syncthreads();
+            t = s_next;
+        }
+        if (t >= ntiles) break;
+        const int4 tile = tiles[t];
+        const Mol &M = mols[tile.x];
+        if (!(skip && M.st->done)) {
+            if ((MIXED ? M.R32 : M.R64) == 2)
+                pair_tile<2, MIXED>(M, tile.y, tile.z, s_pos, s_w64, s_w32);
+            else
+                pair_tile<1, MIXED>(M, tile.y, tile.z, s_pos, s_w64, s_w32);
+        }
+        if (!persistent) break;
     }
-    y[i] = d_top * u[i] - st;
-    y[n + i] = d_bot * u[n + i] - sb;
+}
+
+__global__ void reset_counter_kernel(int *counter) {
+    if (threadIdx.x == 0) *counter = 0;
+}
+
+// ------------------------------------------------------------------ finish
+// MODE kFinishDot: w = D V_j - sum part, partials of <w, V_0>
+//      kFinishRes: res_out = res_b - (D res_x - sum part), partials of ||.||^2
+//      kFinishY:   y = D u - sum part
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void finish_kernel(
+    const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision,
+    int j, int skip) {
+    __shared__ double lds[kBlock / 64];
+    const int2 e = list[blockIdx.x];
+    const Mol &M = mols[e.x];
+    if (skip && M.st->done) return;
+    const int n = M.n, nb = M.nb;
+    const int splits = precision == GABI_FP64 ? M.sp64 : M.sp32;
+    const double *v = MODE == kFinishDot ? M.V + (size_t)j * 2 * n
+                    : MODE == kFinishRes ? M.res_x
+                                         : M.u;
+    double *out = MODE == kFinishDot ? M.w : MODE == kFinishRes ? M.res_out : M.y;
+    const double dt = M.d_top, db = M.d_bot;
+    double s = 0.0;
+    for (int i = e.y * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+        double st = 0.0, sb = 0.0;
+        for (int p = 0; p < splits; ++p) {
+            st += M.part[(size_t)(2 * p) * n + i];
+            sb += M.part[(size_t)(2 * p + 1) * n + i];
+        }
+        double yt = dt * v[i] - st;
+        double yb = db * v[n + i] - sb;
+        if constexpr (MODE == kFinishRes) {
+            yt = M.res_b[i] - yt;
+            yb = M.res_b[n + i] - yb;
+        }
+        out[i] = yt;
+        out[n + i] = yb;
+        if constexpr (MODE == kFinishDot)
+            s = __builtin_fma(yt, M.V[i], __builtin_fma(yb, M.V[n + i], s));
+        else if constexpr (MODE == kFinishRes)
+            s = __builtin_fma(yt, yt, __builtin_fma(yb, yb, s));
+    }
+    if constexpr (MODE != kFinishY) {
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) M.red[e.y] = s;
+    }
 }
 
 // ------------------------------------------------------------------ host
-static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
-
-void launch_prep(gabi_ctx *ctx, int precision, const double *u,
-                 const double *scale, double *store, const int32_t *skip) {
-    const int n = (int)ctx->n;
-    hipLaunchKernelGGL(prep_kernel, dim3(cdiv(n, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, n, ctx->pos, ctx->nrm, u, scale, store,
-                       precision == GABI_FP64 ? ctx->wgt : nullptr,
-                       precision == GABI_FP64 ? nullptr : ctx->wgt32, skip);
+void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip) {
+    const dim3 g(b.n_elem), blk(kBlock);
+    switch (mode) {
+        case kPrepCycle0:
+            hipLaunchKernelGGL(prep_kernel<kPrepCycle0>, g, blk, 0, s, b.d_mols, b.d_elem,
+                               precision, j, (int)skip);
+            break;
+        case kPrepCycleJ:
+            hipLaunchKernelGGL(prep_kernel<kPrepCycleJ>, g, blk, 0, s, b.d_mols, b.d_elem,
+                               precision, j, (int)skip);
+            break;
+        case kPrepResX:
+            hipLaunchKernelGGL(prep_kernel<kPrepResX>, g, blk, 0, s, b.d_mols, b.d_elem,
+                               precision, j, (int)skip);
+            break;
+        case kPrepSol:
+            hipLaunchKernelGGL(prep_kernel<kPrepSol>, g, blk, 0, s, b.d_mols, b.d_elem,
+                               precision, j, (int)skip);
+            break;
+        default:
+            hipLaunchKernelGGL(prep_kernel<kPrepU>, g, blk, 0, s, b.d_mols, b.d_elem,
+                               precision, j, (int)skip);
+            break;
+    }
 }
 
-void launch_pair(gabi_ctx *ctx, int precision, const int32_t *skip) {
-    const int n = (int)ctx->n;
-    const PairLaunch L = pair_launch(n, precision);
-    const double eps = ctx->eps2 / ctx->eps1;
-    PairConstF64 c64{ctx->kappa, eps, 1.0 / eps};
-    PairConstF32 c32{(float)ctx->kappa,
-                     (float)(-ctx->kappa * 1.4426950408889634074), (float)eps,
-                     (float)(1.0 / eps)};
-    dim3 grid(L.row_blocks, L.splits);
-    const int pi = precision == GABI_FP64 ? 0 : 1;
+void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer *t) {
+    const bool mixed = precision != GABI_FP64;
+    const int ntiles = mixed ? b.n_tiles32 : b.n_tiles64;
+    const int4 *tiles = mixed ? b.d_tiles32 : b.d_tiles64;
+    if (ntiles == 0) return;
+    const int pi = mixed ? 1 : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->timing.enabled) {
-        if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
-            (void)hipEventRecord(e0, ctx->stream);
+    if (t && t->pending[pi]) {
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            e0 = e1 = nullptr;
+        } else {
+            (void)hipEventRecord(e0, s);
+        }
     }
-#define GABI_PAIR(R, MX)                                                      \
-    hipLaunchKernelGGL((pair_kernel<R, MX>), grid, dim3(kBlock), 0,           \
-                       ctx->stream, n, L.tiles_per_split, ctx->pos, ctx->nrm, \
-                       ctx->nrm32, ctx->wgt, ctx->wgt32, c64, c32, ctx->part, \
-                       skip)
-    if (precision == GABI_FP64) {
-        if (L.rows_per_thread == 2) GABI_PAIR(2, false);
-        else GABI_PAIR(1, false);
-    } else {
-        if (L.rows_per_thread == 2) GABI_PAIR(2, true);
-        else GABI_PAIR(1, true);
+    int grid = ntiles;
+    if (b.persistent) {
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, b.d_counter);
+        grid = std::min(ntiles, mixed ? b.grid32 : b.grid64);
     }
-#undef GABI_PAIR
+    if (mixed)
+        hipLaunchKernelGGL(pair_kernel<true>, dim3(grid), dim3(kBlock), 0, s, b.d_mols,
+                           tiles, ntiles, b.d_counter, (int)b.persistent, (int)skip);
+    else
+        hipLaunchKernelGGL(pair_kernel<false>, dim3(grid), dim3(kBlock), 0, s, b.d_mols,
+                           tiles, ntiles, b.d_counter, (int)b.persistent, (int)skip);
     if (e0 && e1) {
-        (void)hipEventRecord(e1, ctx->stream);
-        ctx->timing.pending[pi].push_back({e0, e1});
+        (void)hipEventRecord(e1, s);
+        t->pending[pi]->push_back({e0, e1});
     }
 }
 
-void launch_finish(gabi_ctx *ctx, int precision, const double *u, double *y) {
-    const int n = (int)ctx->n;
-    const PairLaunch L = pair_launch(n, precision);
-    const double eps = ctx->eps2 / ctx->eps1;
-    hipLaunchKernelGGL(finish_kernel, dim3(cdiv(n, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, n, L.splits, ctx->part, u,
-                       0.5 * (1.0 + eps), 0.5 * (1.0 + 1.0 / eps), y);
+void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip) {
+    const dim3 g(b.n_blas), blk(kBlock);
+    if (mode == kFinishDot)
+        hipLaunchKernelGGL(finish_kernel<kFinishDot>, g, blk, 0, s, b.d_mols, b.d_blas,
+                           precision, j, (int)skip);
+    else if (mode == kFinishRes)
+        hipLaunchKernelGGL(finish_kernel<kFinishRes>, g, blk, 0, s, b.d_mols, b.d_blas,
+                           precision, j, (int)skip);
+    else
+        hipLaunchKernelGGL(finish_kernel<kFinishY>, g, blk, 0, s, b.d_mols, b.d_blas,
+                           precision, j, (int)skip);
 }
 
-int matvec_device(gabi_ctx *ctx, int precision, const double *u, double *y) {
-    launch_prep(ctx, precision, u, nullptr, nullptr, nullptr);
-    launch_pair(ctx, precision, nullptr);
-    launch_finish(ctx, precision, u, y);
-    GABI_HIP(ctx, hipGetLastError());
-    return GABI_OK;
+int pair_occupancy_grid(int precision) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 1024;
+    hipError_t e = precision == GABI_FP64
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<false>, kBlock, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<true>, kBlock, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * cus;
 }
 
 }  // namespace gabi

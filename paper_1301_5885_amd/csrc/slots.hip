@@ -1,0 +1,343 @@
+// Per-molecule device memory (slots), product decomposition and the tuning
+// table it is read from, and batches (block lists over many molecules).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "gabi_internal.h"
+
+namespace gabi {
+
+// ---------------------------------------------------------------- tuning
+namespace {
+constexpr int kBuckets = 40;
+TuneEntry g_table[2][kBuckets];
+bool g_table_init = false;
+std::mutex g_table_mu;
+
+int bucket_of(int64_t n) {
+    int b = 0;
+    while (b + 1 < kBuckets && (int64_t(1) << (b + 1)) <= n) ++b;
+    return b;
+}
+
+void init_table_locked() {
+    if (g_table_init) return;
+    for (int p = 0; p < 2; ++p)
+        for (int b = 0; b < kBuckets; ++b) {
+            TuneEntry e;
+            e.rows_per_thread = b >= 13 ? 2 : 1;  // N >= 8192: two rows per thread
+            e.target_blocks = 2048;
+            g_table[p][b] = e;
+        }
+    g_table_init = true;
+}
+}  // namespace
+
+TuneEntry tune_entry(int precision, int64_t n) {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    init_table_locked();
+    return g_table[precision == GABI_FP64 ? 0 : 1][bucket_of(n)];
+}
+
+int set_tune_entry(int precision, int bucket, TuneEntry e) {
+    if (bucket < 0 || bucket >= kBuckets) return GABI_EINVAL;
+    if (e.rows_per_thread != 1 && e.rows_per_thread != 2) return GABI_EINVAL;
+    if (e.target_blocks < 1 || e.target_blocks > (1 << 20)) return GABI_EINVAL;
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    init_table_locked();
+    g_table[precision == GABI_FP64 ? 0 : 1][bucket] = e;
+    return GABI_OK;
+}
+
+void reset_tuning() {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    g_table_init = false;
+    init_table_locked();
+}
+
+PairLaunch pair_launch(int64_t n, int precision) {
+    const TuneEntry e = tune_entry(precision, n);
+    PairLaunch L;
+    L.rows_per_thread = e.rows_per_thread;
+    const int64_t rows_per_block = (int64_t)kBlock * L.rows_per_thread;
+    L.row_blocks = (int)((n + rows_per_block - 1) / rows_per_block);
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    int64_t want = (e.target_blocks + L.row_blocks - 1) / L.row_blocks;
+    if (want < 1) want = 1;
+    int64_t tps = (tiles + want - 1) / want;
+    if (tps < 1) tps = 1;
+    L.tiles_per_split = (int)tps;
+    L.splits = (int)((tiles + tps - 1) / tps);
+    return L;
+}
+
+int blas_blocks(int64_t n) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, kBlasBlocksMax));
+}
+
+// ---------------------------------------------------------------- slots
+namespace {
+struct Carver {
+    char *base;
+    int64_t off = 0;
+    template <typename T>
+    T *take(int64_t count) {
+        off = (off + 255) & ~int64_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += std::max<int64_t>(1, count) * (int64_t)sizeof(T);
+        return p;
+    }
+};
+
+void reaction_split(int64_t n, int64_t nc, int &kblocks, int &tps, int &splits) {
+    kblocks = (int)std::max<int64_t>(1, (nc + kBlock - 1) / kBlock);
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    int64_t want = (1024 + kblocks - 1) / kblocks;
+    if (want < 1) want = 1;
+    int64_t t = (tiles + want - 1) / want;
+    if (t < 1) t = 1;
+    tps = (int)t;
+    splits = (int)((tiles + t - 1) / t);
+}
+
+// Lays the buffers of one molecule out in one block starting at base (null:
+// sizing only); returns the size in bytes.
+int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
+    const PairLaunch L64 = pair_launch(n, GABI_FP64), L32 = pair_launch(n, GABI_FP32_PAIR);
+    int kb, tps, sp;
+    reaction_split(n, nc, kb, tps, sp);
+    Carver c{base};
+    const int64_t len = 2 * n;
+    Mol t{};
+    t.pos = c.take<double4>(n);
+    t.nrm = c.take<double4>(n);
+    t.nrm32 = c.take<float4>(n);
+    t.chg = c.take<double4>(nc);
+    t.wgt = c.take<double4>(n);
+    t.wgt32 = c.take<float4>(n);
+    t.part = c.take<double>(len * std::max(L64.splits, L32.splits));
+    t.u = c.take<double>(len);
+    t.y = c.take<double>(len);
+    t.b = c.take<double>(len);
+    t.x = c.take<double>(len);
+    t.r = c.take<double>(len);
+    t.w = c.take<double>(len);
+    t.bo = c.take<double>(len);
+    t.xo = c.take<double>(len);
+    t.sol = c.take<double>(len);
+    t.V = c.take<double>(len * (m + 1));
+    t.H = c.take<double>((int64_t)(m + 1) * m);
+    t.cs = c.take<double>(m);
+    t.sn = c.take<double>(m);
+    t.g = c.take<double>(m + 1);
+    t.hn = c.take<double>(m);
+    t.red = c.take<double>(2 * kBlasBlocksMax);
+    t.st = c.take<KrylovStatus>(1);
+    t.phi = c.take<double>(nc);
+    t.phi_part = c.take<double>(nc * sp);
+    if (M) {
+        t.n = (int32_t)n;
+        t.nc = (int32_t)nc;
+        t.nb = blas_blocks(n);
+        t.m = m;
+        t.R64 = L64.rows_per_thread;
+        t.rb64 = L64.row_blocks;
+        t.tps64 = L64.tiles_per_split;
+        t.sp64 = L64.splits;
+        t.R32 = L32.rows_per_thread;
+        t.rb32 = L32.row_blocks;
+        t.tps32 = L32.tiles_per_split;
+        t.sp32 = L32.splits;
+        t.rx_kblocks = kb;
+        t.rx_tps = tps;
+        t.rx_splits = sp;
+        t.maxit = 100;
+        t.tol0 = 1e-6;
+        t.inner_tol = 1e-5;
+        t.mode = M->mode;
+        // keep parameters already set
+        t.kappa = M->kappa; t.eps = M->eps; t.inv_eps = M->inv_eps;
+        t.d_top = M->d_top; t.d_bot = M->d_bot; t.rhs_scale = M->rhs_scale;
+        t.kappa_f = M->kappa_f; t.nkl2e_f = M->nkl2e_f; t.eps_f = M->eps_f;
+        t.inv_eps_f = M->inv_eps_f;
+        *M = t;
+    }
+    return c.off;
+}
+}  // namespace
+
+int64_t slot_bytes(int64_t n, int64_t nc, int m) { return layout(n, nc, m, nullptr, nullptr); }
+
+void slot_carve(Slot &s, int64_t n, int64_t nc, int m) {
+    layout(n, nc, m, static_cast<char *>(s.mem), &s.mol);
+    slot_set_mode(s, s.mol.mode);
+}
+
+void slot_set_params(Slot &s, double eps1, double eps2, double kappa) {
+    Mol &M = s.mol;
+    const double eps = eps2 / eps1;
+    M.kappa = kappa;
+    M.eps = eps;
+    M.inv_eps = 1.0 / eps;
+    M.d_top = 0.5 * (1.0 + eps);
+    M.d_bot = 0.5 * (1.0 + 1.0 / eps);
+    M.rhs_scale = 1.0 / (4.0 * kPi * eps1);
+    M.kappa_f = (float)kappa;
+    M.nkl2e_f = (float)(-kappa * 1.4426950408889634074);
+    M.eps_f = (float)eps;
+    M.inv_eps_f = (float)(1.0 / eps);
+}
+
+// Role of each vector in the two solvers:
+//   FP64 GMRES:  b = rhs, x = iterate, r = residual (cycle start)
+//   mixed IR:    bo = rhs, xo = iterate, b = FP64 residual bo - A xo, which
+//                is also the right-hand side of the FP32-pair cycle whose
+//                correction V y is added to xo directly.
+void slot_set_mode(Slot &s, int mode) {
+    Mol &M = s.mol;
+    M.mode = mode;
+    if (mode == kModeMixed) {
+        M.rhs_dst = M.bo;
+        M.cyc_src = M.b;
+        M.upd_dst = M.xo;
+        M.res_x = M.xo;
+        M.res_b = M.bo;
+        M.res_out = M.b;
+    } else {
+        M.rhs_dst = M.b;
+        M.cyc_src = M.r;
+        M.upd_dst = M.x;
+        M.res_x = M.x;
+        M.res_b = M.b;
+        M.res_out = M.r;
+    }
+}
+
+void set_solve_targets(Slot &slot, double tol, double inner_tol, int maxit) {
+    slot.mol.tol0 = tol;
+    slot.mol.inner_tol = inner_tol;
+    slot.mol.maxit = maxit;
+}
+
+// ---------------------------------------------------------------- batches
+void batch_free(Batch &b) {
+    if (b.graph) (void)hipGraphExecDestroy(b.graph);
+    b.graph = nullptr;
+    b.graph_valid = false;
+    if (b.d_mem) (void)hipFree(b.d_mem);
+    if (b.h_pinned) (void)hipHostFree(b.h_pinned);
+    b.d_mem = nullptr;
+    b.h_pinned = nullptr;
+    b.h_status = nullptr;
+    b.cap_bytes = 0;
+    b.d_mols = nullptr;
+    b.n_elem = b.n_blas = b.n_tiles64 = b.n_tiles32 = b.n_rx = 0;
+}
+
+int batch_build(Batch &b, hipStream_t stream, std::string &err) {
+    const int nm = (int)b.slots.size();
+    std::vector<Mol> mols((size_t)nm);
+    std::vector<int2> elem, blas;
+    std::vector<int4> t64, t32, rx;
+    for (int k = 0; k < nm; ++k) {
+        const Mol &M = b.slots[k]->mol;
+        mols[k] = M;
+        const int eb = (M.n + kBlock - 1) / kBlock;
+        for (int i = 0; i < eb; ++i) elem.push_back(make_int2(k, i));
+        for (int i = 0; i < M.nb; ++i) blas.push_back(make_int2(k, i));
+        for (int sp = 0; sp < M.sp64; ++sp)
+            for (int rb = 0; rb < M.rb64; ++rb) t64.push_back(make_int4(k, rb, sp, M.R64 * M.tps64));
+        for (int sp = 0; sp < M.sp32; ++sp)
+            for (int rb = 0; rb < M.rb32; ++rb) t32.push_back(make_int4(k, rb, sp, M.R32 * M.tps32));
+        if (M.nc > 0)
+            for (int sp = 0; sp < M.rx_splits; ++sp)
+                for (int kb = 0; kb < M.rx_kblocks; ++kb) rx.push_back(make_int4(k, kb, sp, 0));
+    }
+    // longest tiles first; ties keep molecule and tile order
+    auto by_cost = [](const int4 &a, const int4 &c) { return a.w > c.w; };
+    std::stable_sort(t64.begin(), t64.end(), by_cost);
+    std::stable_sort(t32.begin(), t32.end(), by_cost);
+
+    auto al = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+    const int64_t o_mols = 0;
+    const int64_t o_elem = al(o_mols + (int64_t)sizeof(Mol) * std::max(1, nm));
+    const int64_t o_blas = al(o_elem + (int64_t)sizeof(int2) * std::max<size_t>(1, elem.size()));
+    const int64_t o_t64 = al(o_blas + (int64_t)sizeof(int2) * std::max<size_t>(1, blas.size()));
+    const int64_t o_t32 = al(o_t64 + (int64_t)sizeof(int4) * std::max<size_t>(1, t64.size()));
+    const int64_t o_rx = al(o_t32 + (int64_t)sizeof(int4) * std::max<size_t>(1, t32.size()));
+    const int64_t o_cnt = al(o_rx + (int64_t)sizeof(int4) * std::max<size_t>(1, rx.size()));
+    const int64_t o_st = al(o_cnt + 256);
+    const int64_t total = al(o_st + (int64_t)sizeof(KrylovStatus) * std::max(1, nm));
+
+    if (b.graph) (void)hipGraphExecDestroy(b.graph);
+    b.graph = nullptr;
+    b.graph_valid = false;
+    if (total > b.cap_bytes || !b.d_mem) {
+        if (b.d_mem) (void)hipFree(b.d_mem);
+        if (b.h_pinned) (void)hipHostFree(b.h_pinned);
+        b.d_mem = nullptr;
+        b.h_pinned = nullptr;
+        b.h_status = nullptr;
+        const int64_t cap = std::max<int64_t>(total * 2, 1 << 16);
+        hipError_t e = hipMalloc(&b.d_mem, cap);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b.d_mem = nullptr;
+            err = std::string("batch allocation failed: ") + hipGetErrorString(e);
+            return GABI_ENOMEM;
+        }
+        e = hipHostMalloc(&b.h_pinned, cap, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(b.d_mem);
+            b.d_mem = nullptr;
+            b.h_pinned = nullptr;
+            err = std::string("pinned status allocation failed: ") + hipGetErrorString(e);
+            return GABI_ENOMEM;
+        }
+        b.cap_bytes = cap;
+    }
+    char *base = static_cast<char *>(b.d_mem);
+    b.d_mols = reinterpret_cast<Mol *>(base + o_mols);
+    b.d_elem = reinterpret_cast<int2 *>(base + o_elem);
+    b.d_blas = reinterpret_cast<int2 *>(base + o_blas);
+    b.d_tiles64 = reinterpret_cast<int4 *>(base + o_t64);
+    b.d_tiles32 = reinterpret_cast<int4 *>(base + o_t32);
+    b.d_rx = reinterpret_cast<int4 *>(base + o_rx);
+    b.d_counter = reinterpret_cast<int *>(base + o_cnt);
+    b.d_status = reinterpret_cast<KrylovStatus *>(base + o_st);
+    b.n_elem = (int)elem.size();
+    b.n_blas = (int)blas.size();
+    b.n_tiles64 = (int)t64.size();
+    b.n_tiles32 = (int)t32.size();
+    b.n_rx = (int)rx.size();
+    // stage everything in the pinned buffer, one upload
+    char *h = reinterpret_cast<char *>(b.h_pinned);
+    std::memset(h, 0, (size_t)total);
+    if (nm) std::memcpy(h + o_mols, mols.data(), sizeof(Mol) * nm);
+    if (!elem.empty()) std::memcpy(h + o_elem, elem.data(), sizeof(int2) * elem.size());
+    if (!blas.empty()) std::memcpy(h + o_blas, blas.data(), sizeof(int2) * blas.size());
+    if (!t64.empty()) std::memcpy(h + o_t64, t64.data(), sizeof(int4) * t64.size());
+    if (!t32.empty()) std::memcpy(h + o_t32, t32.data(), sizeof(int4) * t32.size());
+    if (!rx.empty()) std::memcpy(h + o_rx, rx.data(), sizeof(int4) * rx.size());
+    hipError_t e = hipMemcpyAsync(b.d_mem, h, (size_t)total, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        err = std::string("batch upload failed: ") + hipGetErrorString(e);
+        return GABI_EDEVICE;
+    }
+    b.h_status = reinterpret_cast<KrylovStatus *>(h + o_st);
+    static int grid64 = 0, grid32 = 0;
+    if (!grid64) {
+        grid64 = pair_occupancy_grid(GABI_FP64);
+        grid32 = pair_occupancy_grid(GABI_FP32_PAIR);
+    }
+    b.grid64 = grid64;
+    b.grid32 = grid32;
+    return GABI_OK;
+}
+
+}  // namespace gabi
