@@ -68,15 +68,18 @@ typedef enum {
 } gabi_solve_mode;
 
 typedef struct {
-    int32_t restart;   /* m, Krylov steps per cycle (default 10)              */
-    int32_t maxit;     /* cap on Arnoldi steps over the whole solve (100);
-                          in MIXED_IR: per inner solve                        */
-    double tol;        /* stop when ||b - A u|| / ||b|| <= tol (1e-6), FP64 A */
+    int32_t restart;   /* m, Krylov steps per cycle, 1..64 (default 10)       */
+    int32_t maxit;     /* cap on Arnoldi steps over the whole solve (100)     */
+    double tol;        /* stop when ||b - A u|| / ||b|| <= tol (1e-6), with
+                          the residual always formed with the FP64 product    */
     int32_t mode;      /* gabi_solve_mode (GABI_SOLVE_FP64)                   */
-    double inner_tol;  /* MIXED_IR: relative tolerance of each inner solve
-                          (1e-5)                                              */
-    int32_t max_outer; /* MIXED_IR: cap on refinement steps (10)              */
-    int32_t use_graph; /* replay each GMRES cycle as a captured HIP graph (1) */
+    double inner_tol;  /* MIXED_IR: each refinement step is one GMRES(m)
+                          cycle on the FP32-pair product; it stops early once
+                          its estimate falls below inner_tol times the
+                          current residual (1e-5)                             */
+    int32_t max_outer; /* MIXED_IR: cap on refinement steps (20)              */
+    int32_t use_graph; /* replay each round (cycle, update, residual) as a
+                          captured HIP graph when timing is off (1)           */
 } gabi_solve_opts;
 
 typedef struct {
@@ -187,6 +190,96 @@ int64_t gabi_device_bytes(const gabi_ctx *ctx);
 int gabi_set_kernel_timing(gabi_ctx *ctx, int enable);
 int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
                      int64_t *count, int reset);
+
+/* ------------------------------------------------------------------------ */
+/* Many molecules at once.                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* One solve request: a surface as element arrays (as gabi_set_surface), the
+ * charges (as gabi_set_charges) and the parameters (as gabi_set_params).
+ * All arrays are host memory read during the call that takes the problem.
+ * u_out: optional host buffer of 2N doubles that receives the solution; the
+ * caller keeps it valid until the result has been returned.  tag: any
+ * caller value, copied into the result.                                    */
+typedef struct {
+    int64_t n;
+    const double *cx, *cy, *cz, *nx, *ny, *nz, *area;
+    int64_t nc;
+    const double *px, *py, *pz, *q;
+    double eps1, eps2, kappa;
+    double *u_out;
+    int64_t tag;
+} gabi_problem;
+
+typedef struct {
+    int64_t tag;
+    int32_t status;        /* GABI_OK, GABI_NOT_CONVERGED or an error code */
+    double energy;         /* E_sol, kcal/mol                              */
+    gabi_solve_info info;
+    double t_submit;       /* seconds, monotonic clock of the server       */
+    double t_admit;        /* admitted to the device                       */
+    double t_done;         /* result ready                                 */
+    int64_t device_bytes;  /* device memory the solve held                 */
+} gabi_result;
+
+/* Device bytes one solve of n elements and nc charges holds with GMRES(m)
+ * (the unit of admission; the paper's own count is 11N + 6Nc doubles,
+ * Section 2.4, for its host-driven GMRES).                                 */
+int64_t gabi_solve_footprint(int64_t n, int64_t nc, int32_t restart);
+
+/* Solve nprob problems together on `device`: every kernel launch covers all
+ * molecules still iterating (one batched product over a tile queue per
+ * Arnoldi step); a molecule leaves the batch when it converges or reaches
+ * maxit.  Each molecule is decomposed and reduced exactly as when it is
+ * solved alone, so results[k] is bitwise the result of a batch of one.
+ * opts as gabi_solve (shared by all problems).  results: nprob records,
+ * filled in problem order.  Returns GABI_OK when every problem was
+ * processed (per-problem status in results), or an error for the call.   */
+int gabi_batch_solve(int device, int64_t nprob, const gabi_problem *probs,
+                     const gabi_solve_opts *opts, gabi_result *results);
+
+/* Serving: a worker thread owns one device, an arena of budget_bytes of
+ * device memory and a FIFO queue.  A request is admitted when it is at the
+ * head of the queue, fewer than max_slots solves are active and its
+ * footprint fits in the free arena; admitted requests join the running
+ * batch at the next round boundary (continuous batching) and leave it when
+ * done, freeing their memory for the queue.  device = -1 runs the same
+ * scheduler against a host-only executor that performs no arithmetic
+ * (rounds take `mock_round_seconds`, a request finishes after
+ * ceil(N / 4096) rounds) so admission can be exercised without a GPU.     */
+typedef struct gabi_server gabi_server;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed;
+    int64_t queued;          /* waiting for admission                      */
+    int64_t active;          /* on the device                              */
+    int64_t rounds;          /* batched rounds run                         */
+    int64_t max_active;      /* most solves on the device at once          */
+    int64_t bytes_in_use;    /* arena bytes held by active solves          */
+    int64_t peak_bytes;
+    int64_t budget_bytes;
+} gabi_server_stats;
+
+int gabi_server_create(gabi_server **out, int device, int64_t budget_bytes,
+                       int32_t max_slots, const gabi_solve_opts *opts,
+                       double mock_round_seconds);
+/* Copies the problem and queues it; *ticket (may be null) receives a
+ * sequence number.  GABI_EINVAL for bad data, GABI_ENOMEM if its footprint
+ * exceeds the whole budget (it could never be admitted).                   */
+int gabi_server_submit(gabi_server *srv, const gabi_problem *p, int64_t *ticket);
+/* Moves up to max finished results (completion order) into out; *count
+ * receives how many.  Never blocks.                                        */
+int gabi_server_poll(gabi_server *srv, gabi_result *out, int32_t max, int32_t *count);
+/* Blocks until every submitted request has finished or timeout_s elapses;
+ * GABI_EBUSY on timeout.                                                   */
+int gabi_server_drain(gabi_server *srv, double timeout_s);
+int gabi_server_stats_get(gabi_server *srv, gabi_server_stats *out);
+/* Seconds on the server's monotonic clock (the clock of gabi_result).      */
+double gabi_server_clock(gabi_server *srv);
+const char *gabi_server_last_error(gabi_server *srv);
+/* Stops the worker after the current round; unfinished requests are
+ * dropped.  Frees the arena.                                               */
+void gabi_server_destroy(gabi_server *srv);
 
 #ifdef __cplusplus
 }

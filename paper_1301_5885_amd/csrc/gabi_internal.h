@@ -110,6 +110,7 @@ struct Slot {
     double t_submit = 0, t_admit = 0, t_done = 0;
     double *u_out = nullptr;  // caller's host buffer for the solution
     int status = 0;
+    KrylovStatus host_st{};   // last status read back
 };
 
 // Size of the device block of a slot and the carving of its buffers.
@@ -125,10 +126,12 @@ struct Batch {
     Mol *d_mols = nullptr;
     int2 *d_elem = nullptr;   int n_elem = 0;   // (mol, block) over ceil(n/256)
     int2 *d_blas = nullptr;   int n_blas = 0;   // (mol, block) over nb
-    int4 *d_tiles64 = nullptr; int n_tiles64 = 0;  // (mol, row block, split, 0)
-    int4 *d_tiles32 = nullptr; int n_tiles32 = 0;
+    // product tiles (mol, row block, split, cost), two rows per thread first,
+    // then one row per thread: n_tilesXX[0] and n_tilesXX[1] entries
+    int4 *d_tiles64 = nullptr; int n_tiles64[2] = {0, 0};
+    int4 *d_tiles32 = nullptr; int n_tiles32[2] = {0, 0};
     int4 *d_rx = nullptr;     int n_rx = 0;     // (mol, charge block, split, 0)
-    int *d_counter = nullptr;  // tile queue of the persistent product
+    int *d_counter = nullptr;  // tile queues of the persistent product (4)
     KrylovStatus *d_status = nullptr;  // gathered statuses, one per molecule
     KrylovStatus *h_status = nullptr;  // their pinned host mirror (in h_pinned)
     void *h_pinned = nullptr;          // staging for uploads, same layout as d_mem
@@ -193,6 +196,25 @@ enum FinishMode { kFinishDot = 0, kFinishRes = 1, kFinishY = 2 };
 struct Timer {  // optional event pairs around product launches
     std::vector<std::pair<hipEvent_t, hipEvent_t>> *pending[2] = {nullptr, nullptr};
 };
+
+// abi.hip: validation and staging shared with the batched paths
+int validate_surface(int64_t n, const double *cx, const double *cy, const double *cz,
+                     const double *nx, const double *ny, const double *nz,
+                     const double *area, std::string &msg);
+int validate_charges(int64_t nc, const double *px, const double *py, const double *pz,
+                     const double *q, std::string &msg);
+int check_charges_vs_centroids(int64_t n, const double *cx, const double *cy,
+                               const double *cz, int64_t nc, const double *px,
+                               const double *py, const double *pz, std::string &msg);
+int params_valid(double eps1, double eps2, double kappa);
+int opts_check(const gabi_solve_opts *in, gabi_solve_opts *o, std::string &msg);
+int upload_geometry(Slot &sl, const double4 *pos, const double4 *nrm, const float4 *nrm32,
+                    hipStream_t s);
+int upload_charges(Slot &sl, const double *chg4, hipStream_t s);
+void stage_surface(int64_t n, const double *cx, const double *cy, const double *cz,
+                   const double *nx, const double *ny, const double *nz, const double *area,
+                   std::vector<double4> &pos, std::vector<double4> &nrm,
+                   std::vector<float4> &nrm32);
 
 // matvec.hip
 void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);

@@ -196,9 +196,11 @@ __device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
 
 // One workgroup per tile (flat) or a fixed grid draining the tile queue
 // (persistent).  The loop exits for every workgroup once the counter passes
-// the end of the list.
-template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void pair_kernel(
+// the end of the list.  The FP32-pair variant is held to 7 waves per SIMD
+// (at most 72 VGPRs, which it fits without spilling); the FP64 variant
+// needs its registers and runs at 4.
+template <bool MIXED, int R>
+__global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
     const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
     int *__restrict__ counter, int persistent, int skip) {
     __shared__ double4 s_pos[kTile];
@@ -216,12 +218,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(
         if (t >= ntiles) break;
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
-        if (!(skip && M.st->done)) {
-            if ((MIXED ? M.R32 : M.R64) == 2)
-                pair_tile<2, MIXED>(M, tile.y, tile.z, s_pos, s_w64, s_w32);
-            else
-                pair_tile<1, MIXED>(M, tile.y, tile.z, s_pos, s_w64, s_w32);
-        }
+        if (!(skip && M.st->done)) pair_tile<R, MIXED>(M, tile.y, tile.z, s_pos, s_w64, s_w32);
         if (!persistent) break;
     }
 }
@@ -302,11 +299,24 @@ void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, 
     }
 }
 
+template <bool MIXED, int R>
+static void pair_group(Batch &b, hipStream_t s, const int4 *tiles, int ntiles, int *counter,
+                       int grid_cap, bool skip) {
+    if (ntiles == 0) return;
+    int grid = ntiles;
+    if (b.persistent) {
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+        grid = std::min(ntiles, grid_cap);
+    }
+    hipLaunchKernelGGL((pair_kernel<MIXED, R>), dim3(grid), dim3(kBlock), 0, s, b.d_mols, tiles,
+                       ntiles, counter, (int)b.persistent, (int)skip);
+}
+
 void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer *t) {
     const bool mixed = precision != GABI_FP64;
-    const int ntiles = mixed ? b.n_tiles32 : b.n_tiles64;
+    const int *cnt = mixed ? b.n_tiles32 : b.n_tiles64;
     const int4 *tiles = mixed ? b.d_tiles32 : b.d_tiles64;
-    if (ntiles == 0) return;
+    if (cnt[0] + cnt[1] == 0) return;
     const int pi = mixed ? 1 : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (t && t->pending[pi]) {
@@ -316,17 +326,14 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
             (void)hipEventRecord(e0, s);
         }
     }
-    int grid = ntiles;
-    if (b.persistent) {
-        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, b.d_counter);
-        grid = std::min(ntiles, mixed ? b.grid32 : b.grid64);
+    int *c = b.d_counter + (mixed ? 2 : 0);
+    if (mixed) {
+        pair_group<true, 2>(b, s, tiles, cnt[0], c, b.grid32, skip);
+        pair_group<true, 1>(b, s, tiles + cnt[0], cnt[1], c + 1, b.grid32, skip);
+    } else {
+        pair_group<false, 2>(b, s, tiles, cnt[0], c, b.grid64, skip);
+        pair_group<false, 1>(b, s, tiles + cnt[0], cnt[1], c + 1, b.grid64, skip);
     }
-    if (mixed)
-        hipLaunchKernelGGL(pair_kernel<true>, dim3(grid), dim3(kBlock), 0, s, b.d_mols,
-                           tiles, ntiles, b.d_counter, (int)b.persistent, (int)skip);
-    else
-        hipLaunchKernelGGL(pair_kernel<false>, dim3(grid), dim3(kBlock), 0, s, b.d_mols,
-                           tiles, ntiles, b.d_counter, (int)b.persistent, (int)skip);
     if (e0 && e1) {
         (void)hipEventRecord(e1, s);
         t->pending[pi]->push_back({e0, e1});
@@ -352,8 +359,8 @@ int pair_occupancy_grid(int precision) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 1024;
     hipError_t e = precision == GABI_FP64
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<false>, kBlock, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<true>, kBlock, 0);
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<false, 2>, kBlock, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<true, 2>, kBlock, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     return per_cu * cus;
 }

@@ -234,7 +234,8 @@ void batch_free(Batch &b) {
     b.h_status = nullptr;
     b.cap_bytes = 0;
     b.d_mols = nullptr;
-    b.n_elem = b.n_blas = b.n_tiles64 = b.n_tiles32 = b.n_rx = 0;
+    b.n_elem = b.n_blas = b.n_rx = 0;
+    b.n_tiles64[0] = b.n_tiles64[1] = b.n_tiles32[0] = b.n_tiles32[1] = 0;
 }
 
 int batch_build(Batch &b, hipStream_t stream, std::string &err) {
@@ -256,10 +257,24 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
             for (int sp = 0; sp < M.rx_splits; ++sp)
                 for (int kb = 0; kb < M.rx_kblocks; ++kb) rx.push_back(make_int4(k, kb, sp, 0));
     }
-    // longest tiles first; ties keep molecule and tile order
-    auto by_cost = [](const int4 &a, const int4 &c) { return a.w > c.w; };
-    std::stable_sort(t64.begin(), t64.end(), by_cost);
-    std::stable_sort(t32.begin(), t32.end(), by_cost);
+    // group by rows per thread (two first), longest tiles first within a
+    // group; ties keep molecule and tile order
+    auto group = [&](std::vector<int4> &t, bool mixed, int *counts) {
+        auto R = [&](const int4 &a) {
+            const Mol &M = b.slots[a.x]->mol;
+            return mixed ? M.R32 : M.R64;
+        };
+        std::stable_sort(t.begin(), t.end(), [&](const int4 &a, const int4 &c) {
+            const int ra = R(a), rc = R(c);
+            if (ra != rc) return ra > rc;
+            return a.w > c.w;
+        });
+        counts[0] = counts[1] = 0;
+        for (const int4 &a : t) counts[R(a) == 2 ? 0 : 1]++;
+    };
+    int c64[2], c32[2];
+    group(t64, false, c64);
+    group(t32, true, c32);
 
     auto al = [](int64_t v) { return (v + 255) & ~int64_t(255); };
     const int64_t o_mols = 0;
@@ -311,8 +326,10 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     b.d_status = reinterpret_cast<KrylovStatus *>(base + o_st);
     b.n_elem = (int)elem.size();
     b.n_blas = (int)blas.size();
-    b.n_tiles64 = (int)t64.size();
-    b.n_tiles32 = (int)t32.size();
+    b.n_tiles64[0] = c64[0];
+    b.n_tiles64[1] = c64[1];
+    b.n_tiles32[0] = c32[0];
+    b.n_tiles32[1] = c32[1];
     b.n_rx = (int)rx.size();
     // stage everything in the pinned buffer, one upload
     char *h = reinterpret_cast<char *>(b.h_pinned);

@@ -36,7 +36,10 @@ EXPORTS = (
     "gabi_rhs", "gabi_rhs_dev", "gabi_matvec", "gabi_matvec_dev",
     "gabi_solve", "gabi_solve_dev", "gabi_energy", "gabi_energy_dev",
     "gabi_reaction_potential", "gabi_device_bytes", "gabi_set_kernel_timing",
-    "gabi_kernel_time",
+    "gabi_kernel_time", "gabi_solve_footprint", "gabi_batch_solve",
+    "gabi_server_create", "gabi_server_submit", "gabi_server_poll",
+    "gabi_server_drain", "gabi_server_stats_get", "gabi_server_clock",
+    "gabi_server_last_error", "gabi_server_destroy",
 )
 
 
@@ -57,6 +60,34 @@ class SolveInfo(C.Structure):
                 ("matvecs_fp32", C.c_int64), ("restarts", C.c_int64),
                 ("outer", C.c_int64), ("rel_residual", C.c_double),
                 ("converged", C.c_int32), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in
+                                     ("cx", "cy", "cz", "nx", "ny", "nz", "area")] + \
+               [("nc", C.c_int64)] + [(k, C.c_void_p) for k in ("px", "py", "pz", "q")] + \
+               [("eps1", C.c_double), ("eps2", C.c_double), ("kappa", C.c_double),
+                ("u_out", C.c_void_p), ("tag", C.c_int64)]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("status", C.c_int32), ("energy", C.c_double),
+                ("info", SolveInfo), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("device_bytes", C.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "info"}
+        d["info"] = self.info.as_dict()
+        return d
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "submitted", "admitted", "completed", "failed", "queued", "active", "rounds",
+        "max_active", "bytes_in_use", "peak_bytes", "budget_bytes")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,9 +142,27 @@ def load():
     lib.gabi_device_bytes.restype = C.c_int64
     lib.gabi_set_kernel_timing.argtypes = [ctx, C.c_int]
     lib.gabi_kernel_time.argtypes = [ctx, C.c_int, _dp, C.POINTER(C.c_int64), C.c_int]
+    lib.gabi_solve_footprint.argtypes = [_i64, _i64, C.c_int32]
+    lib.gabi_solve_footprint.restype = C.c_int64
+    lib.gabi_batch_solve.argtypes = [C.c_int, _i64, C.POINTER(ProblemC),
+                                     C.POINTER(SolveOpts), C.POINTER(ResultC)]
+    lib.gabi_server_create.argtypes = [C.POINTER(_vp), C.c_int, _i64, C.c_int32,
+                                       C.POINTER(SolveOpts), C.c_double]
+    lib.gabi_server_submit.argtypes = [_vp, C.POINTER(ProblemC), C.POINTER(C.c_int64)]
+    lib.gabi_server_poll.argtypes = [_vp, C.POINTER(ResultC), C.c_int32,
+                                     C.POINTER(C.c_int32)]
+    lib.gabi_server_drain.argtypes = [_vp, C.c_double]
+    lib.gabi_server_stats_get.argtypes = [_vp, C.POINTER(ServerStats)]
+    lib.gabi_server_clock.argtypes = [_vp]
+    lib.gabi_server_clock.restype = C.c_double
+    lib.gabi_server_last_error.argtypes = [_vp]
+    lib.gabi_server_last_error.restype = C.c_char_p
+    lib.gabi_server_destroy.argtypes = [_vp]
+    lib.gabi_server_destroy.restype = None
     for name in EXPORTS:
         if name not in ("gabi_default_opts", "gabi_destroy", "gabi_last_error",
-                        "gabi_device_bytes"):
+                        "gabi_device_bytes", "gabi_solve_footprint", "gabi_server_clock",
+                        "gabi_server_last_error", "gabi_server_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -338,3 +387,118 @@ class Context:
                                                C.byref(cnt), int(bool(reset))),
                     "gabi_kernel_time")
         return ms.value, cnt.value
+
+
+# ---------------------------------------------------------------------------
+# many molecules
+# ---------------------------------------------------------------------------
+def solve_footprint(n, nc, restart=10):
+    """Device bytes one solve holds (the unit of admission)."""
+    return int(load().gabi_solve_footprint(int(n), int(nc), int(restart)))
+
+
+class Request:
+    """One solve request: element arrays, charges, parameters.
+
+    Keeps the numpy arrays alive for as long as the C side may read them."""
+
+    def __init__(self, centroids, normals, area, pos, q, eps1=1.0, eps2=80.0,
+                 kappa=0.1257, tag=0, want_solution=False):
+        c = _f64(centroids).reshape(-1, 3)
+        nrm = _f64(normals).reshape(-1, 3)
+        self.cols = [np.ascontiguousarray(c[:, k]) for k in range(3)] + \
+                    [np.ascontiguousarray(nrm[:, k]) for k in range(3)] + [_f64(area)]
+        pos = _f64(pos).reshape(-1, 3)
+        self.charges = [np.ascontiguousarray(pos[:, k]) for k in range(3)] + [_f64(q)]
+        self.n = c.shape[0]
+        self.nc = pos.shape[0]
+        self.u = np.empty(2 * self.n) if want_solution else None
+        self.c = ProblemC(self.n, *[a.ctypes.data for a in self.cols], self.nc,
+                          *[a.ctypes.data if self.nc else None for a in self.charges],
+                          eps1, eps2, kappa,
+                          self.u.ctypes.data if self.u is not None else None, int(tag))
+
+    @staticmethod
+    def from_mesh(V, F, pos, q, **kw):
+        el = mesh_elements(V, F)
+        c = np.stack([el["cx"], el["cy"], el["cz"]], axis=1)
+        nrm = np.stack([el["nx"], el["ny"], el["nz"]], axis=1)
+        return Request(c, nrm, el["area"], pos, q, **kw)
+
+
+def batch_solve(requests, device=0, **opts):
+    """Solve all requests together; returns one result dict per request."""
+    lib = load()
+    arr = (ProblemC * len(requests))(*[r.c for r in requests])
+    res = (ResultC * len(requests))()
+    o = default_opts(**opts)
+    rc = lib.gabi_batch_solve(int(device), len(requests), arr, C.byref(o), res)
+    if rc != OK:
+        raise GabiError(rc, "gabi_batch_solve")
+    return [r.as_dict() for r in res]
+
+
+class Server:
+    """Serving loop (see include/gabi.h): FIFO admission by device-memory
+    footprint, continuous batching at round boundaries.  device=-1 runs the
+    scheduler with the host-only executor (no arithmetic)."""
+
+    def __init__(self, device=0, budget_bytes=1 << 30, max_slots=64,
+                 mock_round_seconds=0.0, **opts):
+        self._lib = load()
+        h = _vp()
+        o = default_opts(**opts)
+        rc = self._lib.gabi_server_create(C.byref(h), int(device), int(budget_bytes),
+                                          int(max_slots), C.byref(o),
+                                          float(mock_round_seconds))
+        if rc != OK:
+            raise GabiError(rc, "gabi_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, req):
+        t = C.c_int64()
+        rc = self._lib.gabi_server_submit(self._h, C.byref(req.c), C.byref(t))
+        if rc != OK:
+            raise GabiError(rc, self._lib.gabi_server_last_error(self._h).decode())
+        self._keep[req.c.tag] = req
+        return t.value
+
+    def poll(self, max_results=256):
+        buf = (ResultC * max_results)()
+        cnt = C.c_int32()
+        rc = self._lib.gabi_server_poll(self._h, buf, max_results, C.byref(cnt))
+        if rc != OK:
+            raise GabiError(rc, "gabi_server_poll")
+        out = [buf[i].as_dict() for i in range(cnt.value)]
+        return out
+
+    def drain(self, timeout_s=600.0):
+        return self._lib.gabi_server_drain(self._h, float(timeout_s)) == OK
+
+    def stats(self):
+        st = ServerStats()
+        rc = self._lib.gabi_server_stats_get(self._h, C.byref(st))
+        if rc != OK:
+            raise GabiError(rc, "gabi_server_stats_get")
+        return st.as_dict()
+
+    def clock(self):
+        return float(self._lib.gabi_server_clock(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gabi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,136 @@
+"""GPU: batched solves, the serving loop and graph replay.
+
+A molecule is decomposed and reduced the same way alone or among others, so
+its result must be bitwise identical whether it is solved through a context,
+in a batch, or by the server among other requests -- for the FP64 solver and
+for mixed refinement alike.  Batched energies also match the CPU oracle.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_5885_amd import gabi
+from paper_1301_5885_amd.synth import charges_in_star, icosphere, star_surface
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mix():
+    """Molecules of uneven size (ragged tails, both rows-per-thread
+    layouts), different kappa and charge counts."""
+    out = []
+    for k, (nu, R, nc, kappa) in enumerate([(8, 8.0, 30, 0.1257), (11, 10.0, 60, 0.0),
+                                            (15, 14.0, 110, 0.3), (23, 20.0, 200, 0.05),
+                                            (9, 9.0, 1, 0.2)]):
+        rng = np.random.default_rng(100 + k)
+        V, F, shape = star_surface(nu, R, rng)
+        pos = charges_in_star(rng, shape, nc, 0.8)
+        q = rng.normal(0.0, 0.5, nc)
+        out.append((V, F, pos, q, kappa))
+    return out
+
+
+def alone(problems, **opts):
+    res = []
+    with gabi.Context(0) as ctx:
+        for V, F, pos, q, kappa in problems:
+            ctx.set_surface_mesh(V, F)
+            ctx.set_charges(pos, q)
+            ctx.set_params(1.0, 80.0, kappa)
+            u, info = ctx.solve(**opts)
+            res.append((u, ctx.energy(), info))
+    return res
+
+
+def requests(problems):
+    return [gabi.Request.from_mesh(V, F, pos, q, kappa=kappa, tag=i, want_solution=True)
+            for i, (V, F, pos, q, kappa) in enumerate(problems)]
+
+
+@pytest.mark.parametrize("mode", [gabi.SOLVE_FP64, gabi.SOLVE_MIXED_IR])
+def test_batch_is_bitwise_alone(mode):
+    probs = mix()
+    log(f"[batch vs alone] mode={mode} N={[len(p[1]) for p in probs]}")
+    ref = alone(probs, tol=1e-8, mode=mode)
+    reqs = requests(probs)
+    res = gabi.batch_solve(reqs, tol=1e-8, mode=mode)
+    for (u, E, info), r, req in zip(ref, res, reqs):
+        assert r["status"] == gabi.OK
+        assert r["info"]["iterations"] == info["iterations"]
+        assert r["energy"] == E
+        assert np.array_equal(req.u, u)
+
+
+def test_batch_energies_match_oracle():
+    probs = mix()
+    res = gabi.batch_solve(requests(probs), tol=1e-10, mode=gabi.SOLVE_MIXED_IR)
+    for (V, F, pos, q, kappa), r in zip(probs, res):
+        el = oracle.mesh_elements(V, F)
+        _, E, info = oracle.solve(el, pos, q, 1.0, 80.0, kappa, tol=1e-12, maxit=1000)
+        log(f"    N={el.n} E={r['energy']:.10f} oracle={E:.10f}")
+        assert abs(r["energy"] / E - 1) <= 1e-7
+
+
+def test_server_same_alone_and_in_the_mix():
+    probs = mix()
+    ref = alone(probs, tol=1e-8, mode=gabi.SOLVE_MIXED_IR)
+    reqs = requests(probs)
+    budget = 3 * max(gabi.solve_footprint(r.n, r.nc, 10) for r in reqs)
+    with gabi.Server(device=0, budget_bytes=budget, max_slots=3, tol=1e-8,
+                     mode=gabi.SOLVE_MIXED_IR) as s:
+        for r in reqs:
+            s.submit(r)
+            time.sleep(0.002)
+        assert s.drain(120.0)
+        res = sorted(s.poll(), key=lambda r: r["tag"])
+        st = s.stats()
+    log(f"    stats {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert 2 <= st["max_active"] <= 3 and st["peak_bytes"] <= budget
+    for (u, E, info), r, req in zip(ref, res, reqs):
+        assert r["status"] == gabi.OK
+        assert r["energy"] == E
+        assert np.array_equal(req.u, u)
+
+
+def test_graph_replay_matches_eager():
+    """Rounds replayed from a captured graph give the eager result on every
+    replay, with eager work (products) in between."""
+    V, F = icosphere(12, 9.0)
+    rng = np.random.default_rng(4)
+    pos = rng.normal(size=(20, 3))
+    pos *= (5.0 / np.linalg.norm(pos, axis=1))[:, None] * rng.random(20)[:, None]
+    q = rng.normal(size=20)
+    with gabi.Context(0) as ctx:
+        ctx.set_surface_mesh(V, F)
+        ctx.set_charges(pos, q)
+        ctx.set_params(1.0, 80.0, 0.1257)
+        u_eager, i_eager = ctx.solve(tol=1e-10, use_graph=0)
+        v = rng.normal(size=2 * len(F))
+        y0 = ctx.matvec(v)
+        for _ in range(3):
+            u_graph, i_graph = ctx.solve(tol=1e-10, use_graph=1)
+            assert i_graph["restarts"] >= 2          # several replays per solve
+            assert np.array_equal(u_graph, u_eager)
+            assert np.array_equal(ctx.matvec(v), y0)
+        for mode in (gabi.SOLVE_MIXED_IR,):
+            a, _ = ctx.solve(tol=1e-10, use_graph=0, mode=mode)
+            b, _ = ctx.solve(tol=1e-10, use_graph=1, mode=mode)
+            assert np.array_equal(a, b)
+
+
+def test_batch_handles_failures_per_problem():
+    probs = mix()[:3]
+    reqs = requests(probs)
+    res = gabi.batch_solve(reqs, tol=1e-14, maxit=3)
+    for r in res:
+        assert r["status"] == gabi.NOT_CONVERGED
+        assert r["info"]["iterations"] == 3

@@ -1,0 +1,118 @@
+"""Serving scheduler on the CPU (host-only executor: no arithmetic, rounds
+take a fixed time, a request of N elements finishes after ceil(N/4096)
+rounds).  Checks admission by device-memory footprint, the slot limit, FIFO
+order, rejection of requests larger than the budget, and that requests
+overlap (continuous batching)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1301_5885_amd import gabi
+from paper_1301_5885_amd.synth import charges_in_ball, icosphere
+
+
+def request(nu, tag, nc=5, seed=0):
+    V, F = icosphere(nu, 3.0 + nu / 4.0)
+    rng = np.random.default_rng(seed)
+    pos = charges_in_ball(rng, nc, 2.0)
+    q = rng.normal(size=nc)
+    return gabi.Request.from_mesh(V, F, pos, q, tag=tag)
+
+
+def run(server, reqs, gap=0.0):
+    for r in reqs:
+        server.submit(r)
+        if gap:
+            time.sleep(gap)
+    assert server.drain(60.0)
+    out = []
+    while True:
+        got = server.poll()
+        if not got:
+            break
+        out += got
+    return sorted(out, key=lambda r: r["tag"]), server.stats()
+
+
+def test_footprint_accounting():
+    f = [gabi.solve_footprint(20 * nu * nu, 50, 10) for nu in (4, 8, 16)]
+    assert f[0] < f[1] < f[2]
+    assert gabi.solve_footprint(1280, 10, 20) > gabi.solve_footprint(1280, 10, 10)
+    assert gabi.solve_footprint(1280, 1000, 10) > gabi.solve_footprint(1280, 10, 10)
+    # at least the paper's 11N + 6Nc doubles
+    assert gabi.solve_footprint(1280, 10, 10) >= 8 * (11 * 1280 + 6 * 10)
+    assert gabi.solve_footprint(0, 0, 10) == -1
+
+
+def test_tiny_budget_serialises_and_nothing_fails():
+    reqs = [request(8, tag=i, seed=i) for i in range(6)]
+    fp = gabi.solve_footprint(reqs[0].n, reqs[0].nc, 10)
+    with gabi.Server(device=-1, budget_bytes=int(1.5 * fp), max_slots=8,
+                     mock_round_seconds=0.002) as s:
+        res, st = run(s, reqs)
+    assert [r["tag"] for r in res] == list(range(6))
+    assert all(r["status"] == gabi.OK for r in res)
+    assert st["completed"] == 6 and st["failed"] == 0
+    assert st["max_active"] == 1
+    assert st["peak_bytes"] <= int(1.5 * fp)
+    # FIFO: admitted in submission order, each after the previous finished
+    for a, b in zip(res, res[1:]):
+        assert a["t_admit"] <= b["t_admit"]
+        assert b["t_admit"] >= a["t_done"]
+
+
+def test_slot_limit_and_overlap():
+    reqs = [request(8 + (i % 3) * 8, tag=i, seed=i) for i in range(9)]
+    with gabi.Server(device=-1, budget_bytes=1 << 34, max_slots=3,
+                     mock_round_seconds=0.002) as s:
+        res, st = run(s, reqs)
+    assert st["max_active"] == 3
+    assert st["completed"] == 9 and st["failed"] == 0
+    # continuous batching: some request is admitted while an earlier one runs
+    overlap = any(b["t_admit"] < a["t_done"] for a in res for b in res
+                  if b["tag"] > a["tag"])
+    assert overlap
+    # results carry the footprint they held and sane timestamps
+    for r in res:
+        assert r["device_bytes"] == gabi.solve_footprint(reqs[r["tag"]].n, reqs[r["tag"]].nc, 10)
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+
+
+def test_late_arrivals_join_running_batch():
+    big = request(32, tag=0)          # 20480 elements: 5 rounds
+    small = [request(8, tag=i, seed=i) for i in range(1, 4)]
+    with gabi.Server(device=-1, budget_bytes=1 << 34, max_slots=8,
+                     mock_round_seconds=0.01) as s:
+        s.submit(big)
+        time.sleep(0.015)
+        for r in small:
+            s.submit(r)
+        assert s.drain(30.0)
+        res = sorted(s.poll(), key=lambda r: r["tag"])
+        st = s.stats()
+    assert len(res) == 4
+    assert all(r["t_admit"] < res[0]["t_done"] for r in res[1:])
+    assert all(r["t_done"] < res[0]["t_done"] for r in res[1:])
+    assert st["max_active"] >= 2
+
+
+def test_oversize_request_rejected():
+    r = request(16, tag=1)
+    with gabi.Server(device=-1, budget_bytes=1 << 20, max_slots=4) as s:
+        with pytest.raises(gabi.GabiError) as e:
+            s.submit(r)
+        assert e.value.code == gabi.ENOMEM
+        assert s.stats()["submitted"] == 0
+
+
+def test_invalid_request_rejected():
+    V, F = icosphere(4, 2.0)
+    el = gabi.mesh_elements(V, F)
+    c = np.stack([el["cx"], el["cy"], el["cz"]], axis=1)
+    nrm = np.stack([el["nx"], el["ny"], el["nz"]], axis=1)
+    bad = gabi.Request(c, nrm, el["area"], c[3:4], [1.0])   # charge on a centroid
+    with gabi.Server(device=-1, budget_bytes=1 << 30, max_slots=4) as s:
+        with pytest.raises(gabi.GabiError) as e:
+            s.submit(bad)
+        assert e.value.code == gabi.EINVAL
