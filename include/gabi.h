@@ -192,6 +192,21 @@ int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
                      int64_t *count, int reset);
 
 /* ------------------------------------------------------------------------ */
+/* Decomposition of the product (tuning table).                             */
+/* ------------------------------------------------------------------------ */
+
+/* A product of N elements is split into row blocks of 256 * rows_per_thread
+ * targets and into source splits so that about target_blocks workgroups
+ * run (the split partials are added in split order).  The table holds one
+ * (rows_per_thread, target_blocks) per precision and N bucket
+ * (bucket = floor(log2 N), 0..39).  The decomposition fixes the summation
+ * order, so set the table before creating contexts or servers: every solve
+ * made under one table is bitwise reproducible.  rows_per_thread is 1 or 2;
+ * target_blocks in [1, 2^20].  GABI_EINVAL otherwise.                       */
+int gabi_tune_set(int precision, int bucket, int rows_per_thread, int target_blocks);
+int gabi_tune_get(int precision, int bucket, int *rows_per_thread, int *target_blocks);
+
+/* ------------------------------------------------------------------------ */
 /* Many molecules at once.                                                  */
 /* ------------------------------------------------------------------------ */
 

@@ -73,6 +73,29 @@ PairLaunch pair_launch(int64_t n, int precision) {
     return L;
 }
 
+}  // namespace gabi
+
+extern "C" int gabi_tune_set(int precision, int bucket, int rows_per_thread,
+                             int target_blocks) {
+    if (precision != GABI_FP64 && precision != GABI_FP32_PAIR) return GABI_EINVAL;
+    gabi::TuneEntry e;
+    e.rows_per_thread = rows_per_thread;
+    e.target_blocks = target_blocks;
+    return gabi::set_tune_entry(precision, bucket, e);
+}
+
+extern "C" int gabi_tune_get(int precision, int bucket, int *rows_per_thread,
+                             int *target_blocks) {
+    if ((precision != GABI_FP64 && precision != GABI_FP32_PAIR) || bucket < 0 || bucket >= 40)
+        return GABI_EINVAL;
+    const gabi::TuneEntry e = gabi::tune_entry(precision, int64_t(1) << bucket);
+    if (rows_per_thread) *rows_per_thread = e.rows_per_thread;
+    if (target_blocks) *target_blocks = e.target_blocks;
+    return GABI_OK;
+}
+
+namespace gabi {
+
 int blas_blocks(int64_t n) {
     int64_t b = (n + kBlock - 1) / kBlock;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, kBlasBlocksMax));

@@ -39,8 +39,12 @@ EXPORTS = (
     "gabi_kernel_time", "gabi_solve_footprint", "gabi_batch_solve",
     "gabi_server_create", "gabi_server_submit", "gabi_server_poll",
     "gabi_server_drain", "gabi_server_stats_get", "gabi_server_clock",
-    "gabi_server_last_error", "gabi_server_destroy",
+    "gabi_server_last_error", "gabi_server_destroy", "gabi_tune_set", "gabi_tune_get",
 )
+
+# Tuned decomposition table for gfx950, applied when the library is loaded
+# (set GABI_TUNING=none to keep the built-in defaults, or to another path).
+TUNING_PATH = os.path.join(HERE, "tuning_gfx950.json")
 
 
 class GabiError(RuntimeError):
@@ -142,6 +146,8 @@ def load():
     lib.gabi_device_bytes.restype = C.c_int64
     lib.gabi_set_kernel_timing.argtypes = [ctx, C.c_int]
     lib.gabi_kernel_time.argtypes = [ctx, C.c_int, _dp, C.POINTER(C.c_int64), C.c_int]
+    lib.gabi_tune_set.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.gabi_tune_get.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.gabi_solve_footprint.argtypes = [_i64, _i64, C.c_int32]
     lib.gabi_solve_footprint.restype = C.c_int64
     lib.gabi_batch_solve.argtypes = [C.c_int, _i64, C.POINTER(ProblemC),
@@ -165,7 +171,38 @@ def load():
                         "gabi_server_last_error", "gabi_server_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
+    _apply_tuning(lib)
     return lib
+
+
+def _apply_tuning(lib):
+    import json
+    path = os.environ.get("GABI_TUNING", TUNING_PATH)
+    if path == "none" or not os.path.exists(path):
+        return
+    with open(path) as f:
+        table = json.load(f)
+    for key, prec in (("fp64", FP64), ("fp32", FP32_PAIR)):
+        for bucket, e in table.get("entries", {}).get(key, {}).items():
+            rc = lib.gabi_tune_set(prec, int(bucket), int(e["rows_per_thread"]),
+                                   int(e["target_blocks"]))
+            if rc != OK:
+                raise GabiError(rc, f"bad tuning entry {key}/{bucket} in {path}")
+
+
+def tune_set(precision, bucket, rows_per_thread, target_blocks):
+    rc = load().gabi_tune_set(int(precision), int(bucket), int(rows_per_thread),
+                              int(target_blocks))
+    if rc != OK:
+        raise GabiError(rc, "gabi_tune_set")
+
+
+def tune_get(precision, bucket):
+    r, t = C.c_int(), C.c_int()
+    rc = load().gabi_tune_get(int(precision), int(bucket), C.byref(r), C.byref(t))
+    if rc != OK:
+        raise GabiError(rc, "gabi_tune_get")
+    return r.value, t.value
 
 
 def _f64(a):
