@@ -16,8 +16,13 @@ Printed (one JSON line on stdout):
              around every launch on the solver's stream, timed region only)
              against the published FP32 vector peak.
   cpu_baseline  the FP64 CPU oracle's product on the host cores.
+  serving    solves/s and p50/p99 latency of the plain FP64 solver, the
+             plain mixed solver and the served (batched, memory-admitted)
+             mixed solver on a stream of uneven requests
+             (paper_1301_5885_amd/serve.py).
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload kirkwood]
+                       [--serve-requests 64]
 """
 from __future__ import annotations
 
@@ -44,6 +49,12 @@ WORKLOADS = {
     "born": "Born ion: sphere R=2 A, nu=8 (N=1280), one +1 charge at the centre; "
             "eps1=1, eps2=80, kappa=0.1257/A; GMRES(10) to rel. residual 1e-8",
 }
+
+
+SERVING_WORKLOAD = ("the first requests of a seeded 512-request stream: star-shaped surfaces, "
+                    "N = 20 nu^2 log-uniform in [1280, 81920], Nc = N/40, Q~N(0,0.5^2) inside "
+                    "0.8 r, kappa~U[0,0.3]; Poisson arrivals at 0.8 x the plain FP64 solver's "
+                    "throughput, plus a saturation run")
 
 
 def log(*a):
@@ -113,7 +124,7 @@ def run_solver(ctx, gabi, torch, u, mode, steps, warmup, pairs):
     }
 
 
-def roofline(res, key, n, workload):
+def roofline(res, key, n, workload, gabi=None):
     products = res["products_fp32" if key == "fp32" else "products_fp64"]
     if products == 0:
         return None
@@ -124,9 +135,13 @@ def roofline(res, key, n, workload):
     achieved = flop / avg_s / 1e12
     peak = PEAK_TFLOPS[key]
     t = traffic_from_profiles(f"pair_{key}", workload)
+    bucket = n.bit_length() - 1
+    R, blocks = gabi.tune_get(gabi.FP32_PAIR if key == "fp32" else gabi.FP64, bucket)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": t, "kernel": f"pair_kernel<{key}>",
+            "traffic": t,
+            "kernel": f"gabi::pair_kernel<{'true' if key == 'fp32' else 'false'}, {R}>",
+            "target_blocks": blocks,
             "avg_launch_ms": round(avg_s * 1e3, 5),
             "flop_per_launch": flop}
 
@@ -158,6 +173,10 @@ def main():
     ap.add_argument("--workload", default="kirkwood", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving stream to serve after the single-solve "
+                         "timing (0: skip; the stream has 512)")
+    ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run one device copy of this many MiB "
                          "(a kernel of known traffic for scaling HBM counters)")
@@ -167,6 +186,13 @@ def main():
               "supported (the row-sharded multi-GPU product is a design only)",
               file=sys.stderr)
         sys.exit(2)
+
+    from paper_1301_5885_amd import serve
+    serve_problems = None
+    if args.serve_requests > 0:
+        # generated in a process pool, before anything touches the GPU
+        log(f"[bench] generating {args.serve_requests} serving requests")
+        serve_problems = serve.make_problems(args.serve_requests, 16)
 
     import torch
     from paper_1301_5885_amd import gabi
@@ -221,23 +247,28 @@ def main():
         "energy_rel_err": mixed["energy_rel_err"],
         "products_per_solve": {"fp32": mixed["products_fp32"] / args.steps,
                                "fp64": mixed["products_fp64"] / args.steps},
-        "roofline": roofline(mixed, "fp32", n, args.workload),
+        "roofline": roofline(mixed, "fp32", n, args.workload, gabi),
         "fp64_solver": {
             "value": round(fp64["gpairs_per_s"], 3), "unit": "Gpair-kernels/s",
             "solves_per_s": round(fp64["solves_per_s"], 3),
             "ms_per_step": round(fp64["ms_per_step"], 4),
             "energy_rel_err": fp64["energy_rel_err"],
             "products_per_solve": fp64["products_fp64"] / args.steps,
-            "roofline": roofline(fp64, "fp64", n, args.workload),
+            "roofline": roofline(fp64, "fp64", n, args.workload, gabi),
         },
         "speedup_mixed_over_fp64": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3),
     }
+    ctx.close()
+    if serve_problems is not None:
+        log(f"[bench] serving {args.serve_requests} requests")
+        line["serving"] = serve.run(args.serve_requests, args.serve_slots,
+                                    problems=serve_problems)
+        line["serving"]["workload"] = SERVING_WORKLOAD
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (oracle, ~{args.cpu_seconds:.0f} s)")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     else:
         line["cpu_baseline"] = None
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

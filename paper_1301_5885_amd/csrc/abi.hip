@@ -174,7 +174,7 @@ int opts_check(const gabi_solve_opts *in, gabi_solve_opts *o, std::string &msg) 
 }
 
 // Upload of staged host data into a carved slot (synchronous on stream s).
-int upload_geometry(Slot &sl, const double4 *pos, const double4 *nrm, const float4 *nrm32,
+int upload_geometry(Slot &sl, const double4 *pos, const double4 *nrm, const float4 *geo32,
                     hipStream_t s) {
     const int64_t n = sl.mol.n;
     hipError_t e = hipMemcpyAsync((void *)sl.mol.pos, pos, sizeof(double4) * n,
@@ -182,7 +182,7 @@ int upload_geometry(Slot &sl, const double4 *pos, const double4 *nrm, const floa
     if (e == hipSuccess)
         e = hipMemcpyAsync((void *)sl.mol.nrm, nrm, sizeof(double4) * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync((void *)sl.mol.nrm32, nrm32, sizeof(float4) * n,
+        e = hipMemcpyAsync((void *)sl.mol.pos32, geo32, sizeof(float4) * 2 * n,
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e == hipSuccess ? GABI_OK : GABI_EDEVICE;
@@ -199,14 +199,27 @@ int upload_charges(Slot &sl, const double *chg4, hipStream_t s) {
 void stage_surface(int64_t n, const double *cx, const double *cy, const double *cz,
                    const double *nx, const double *ny, const double *nz, const double *area,
                    std::vector<double4> &pos, std::vector<double4> &nrm,
-                   std::vector<float4> &nrm32) {
+                   std::vector<float4> &geo32) {
     pos.resize((size_t)n);
     nrm.resize((size_t)n);
-    nrm32.resize((size_t)n);
+    geo32.resize((size_t)(2 * n));
+    // FP32 coordinates for the mixed product are taken relative to the centre
+    // of the bounding box, which keeps their magnitude (and so their
+    // rounding error) as small as a single origin allows.
+    double lo[3] = {cx[0], cy[0], cz[0]}, hi[3] = {cx[0], cy[0], cz[0]};
+    for (int64_t i = 1; i < n; ++i) {
+        lo[0] = std::min(lo[0], cx[i]), hi[0] = std::max(hi[0], cx[i]);
+        lo[1] = std::min(lo[1], cy[i]), hi[1] = std::max(hi[1], cy[i]);
+        lo[2] = std::min(lo[2], cz[i]), hi[2] = std::max(hi[2], cz[i]);
+    }
+    const double ox = 0.5 * (lo[0] + hi[0]), oy = 0.5 * (lo[1] + hi[1]),
+                 oz = 0.5 * (lo[2] + hi[2]);
     for (int64_t i = 0; i < n; ++i) {
         pos[i] = make_double4(cx[i], cy[i], cz[i], area[i]);
         nrm[i] = make_double4(nx[i], ny[i], nz[i], 0.0);
-        nrm32[i] = make_float4((float)nx[i], (float)ny[i], (float)nz[i], 0.0f);
+        geo32[i] = make_float4((float)(cx[i] - ox), (float)(cy[i] - oy), (float)(cz[i] - oz),
+                               0.0f);
+        geo32[n + i] = make_float4((float)nx[i], (float)ny[i], (float)nz[i], 0.0f);
     }
 }
 
@@ -256,7 +269,7 @@ int ensure_slot(gabi_ctx *ctx, int m) {
     }
     if (ctx->geom_dirty) {
         if (upload_geometry(ctx->slot, ctx->host_pos.data(), ctx->host_nrm.data(),
-                            ctx->host_nrm32.data(), ctx->stream))
+                            ctx->host_geo32.data(), ctx->stream))
             return fail(ctx, GABI_EDEVICE, "geometry upload failed");
         ctx->geom_dirty = false;
     }
@@ -425,7 +438,7 @@ int gabi_set_surface(gabi_ctx *ctx, int64_t n, const double *cx,
         if (rc) return fail(ctx, rc, msg);
     }
     stage_surface(n, cx, cy, cz, nx, ny, nz, area, ctx->host_pos, ctx->host_nrm,
-                  ctx->host_nrm32);
+                  ctx->host_geo32);
     ctx->host_centroids.resize((size_t)(3 * n));
     for (int64_t i = 0; i < n; ++i) {
         ctx->host_centroids[3 * i] = cx[i];

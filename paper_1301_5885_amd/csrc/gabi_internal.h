@@ -78,7 +78,8 @@ struct Mol {
     float kappa_f, nkl2e_f, eps_f, inv_eps_f;
     const double4 *pos;   // (cx, cy, cz, area)
     const double4 *nrm;   // (nx, ny, nz, 0)
-    const float4 *nrm32;
+    const float4 *pos32;  // FP32 (x, y, z, 0) relative to the bounding-box centre
+    const float4 *nrm32;  // FP32 (nx, ny, nz, 0); follows pos32 in memory
     const double4 *chg;   // (x, y, z, q)
     double4 *wgt;         // (s, mx, my, mz)
     float4 *wgt32;
@@ -98,6 +99,10 @@ struct Mol {
 // Host-side record of one molecule: its descriptor plus bookkeeping.
 struct Slot {
     Mol mol{};
+    // Unique per admission (never reused, unlike the Slot's address, which
+    // the allocator hands out again once a finished slot is freed): batches
+    // are compared by these ids to decide whether they must be rebuilt.
+    int64_t uid = 0;
     void *mem = nullptr;      // one device block holding every buffer
     int64_t bytes = 0;
     bool from_arena = false;
@@ -112,6 +117,8 @@ struct Slot {
     int status = 0;
     KrylovStatus host_st{};   // last status read back
 };
+
+int64_t next_slot_uid();
 
 // Size of the device block of a slot and the carving of its buffers.
 int64_t slot_bytes(int64_t n, int64_t nc, int m);
@@ -170,7 +177,7 @@ struct gabi_ctx {
     std::vector<double> host_centroids;  // 3n, for validation
     std::vector<double> host_charges;    // 4nc
     std::vector<double4> host_pos, host_nrm;
-    std::vector<float4> host_nrm32;
+    std::vector<float4> host_geo32;  // pos32 then nrm32 (2n)
 
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
@@ -208,13 +215,13 @@ int check_charges_vs_centroids(int64_t n, const double *cx, const double *cy,
                                const double *py, const double *pz, std::string &msg);
 int params_valid(double eps1, double eps2, double kappa);
 int opts_check(const gabi_solve_opts *in, gabi_solve_opts *o, std::string &msg);
-int upload_geometry(Slot &sl, const double4 *pos, const double4 *nrm, const float4 *nrm32,
+int upload_geometry(Slot &sl, const double4 *pos, const double4 *nrm, const float4 *geo32,
                     hipStream_t s);
 int upload_charges(Slot &sl, const double *chg4, hipStream_t s);
 void stage_surface(int64_t n, const double *cx, const double *cy, const double *cz,
                    const double *nx, const double *ny, const double *nz, const double *area,
                    std::vector<double4> &pos, std::vector<double4> &nrm,
-                   std::vector<float4> &nrm32);
+                   std::vector<float4> &geo32);
 
 // matvec.hip
 void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);

@@ -193,9 +193,9 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const Mol *__restrict__ 
     __shared__ double y[kMaxRestart];
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
-    const int k = M.st->k;
-    if (k == 0) return;
     const int m = M.m, n = M.n;
+    const int k = min(max(M.st->k, 0), m);
+    if (k == 0) return;
     if (threadIdx.x == 0) {
         for (int i = k - 1; i >= 0; --i) {
             double s = M.g[i];

@@ -69,19 +69,65 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
 }
 
 // ------------------------------------------------------------------ pair
+// Per-precision views of a molecule: the FP64 product reads FP64 centroids
+// (cx, cy, cz, area) and weights (s, mx, my, mz); the FP32 one reads the
+// centred FP32 coordinates and FP32 weights.
+template <bool MIXED> struct PairView;
+template <> struct PairView<false> {
+    using T = double;
+    using T4 = double4;
+    static __device__ __forceinline__ const T4 *pos(const Mol &M) { return M.pos; }
+    static __device__ __forceinline__ const T4 *nrm(const Mol &M) { return M.nrm; }
+    static __device__ __forceinline__ const T4 *wgt(const Mol &M) { return M.wgt; }
+    static __device__ __forceinline__ int tps(const Mol &M) { return M.tps64; }
+};
+template <> struct PairView<true> {
+    using T = float;
+    using T4 = float4;
+    static __device__ __forceinline__ const T4 *pos(const Mol &M) { return M.pos32; }
+    static __device__ __forceinline__ const T4 *nrm(const Mol &M) { return M.nrm32; }
+    static __device__ __forceinline__ const T4 *wgt(const Mol &M) { return M.wgt32; }
+    static __device__ __forceinline__ int tps(const Mol &M) { return M.tps32; }
+};
+
+template <bool MIXED>
+__device__ __forceinline__ void pair_eval(const Mol &M, typename PairView<MIXED>::T tx,
+                                          typename PairView<MIXED>::T ty,
+                                          typename PairView<MIXED>::T tz,
+                                          typename PairView<MIXED>::T tnx,
+                                          typename PairView<MIXED>::T tny,
+                                          typename PairView<MIXED>::T tnz,
+                                          const typename PairView<MIXED>::T4 &p,
+                                          const typename PairView<MIXED>::T4 &w,
+                                          typename PairView<MIXED>::T &top,
+                                          typename PairView<MIXED>::T &bot) {
+    if constexpr (MIXED) {
+        const PairConstF32 c{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
+        pair_f32(c, tx, ty, tz, tnx, tny, tnz, p.x, p.y, p.z, w.x, w.y, w.z, w.w, top, bot);
+    } else {
+        const PairConstF64 c{M.kappa, M.eps, M.inv_eps};
+        pair_f64(c, tx, ty, tz, tnx, tny, tnz, p.x, p.y, p.z, w.x, w.y, w.z, w.w, top, bot);
+    }
+}
+
+// One tile: R target rows per thread against the split's sources.  The FP64
+// product accumulates each row in FP64 directly; the FP32 product sums each
+// 256-source stage in FP32 and adds the stage sum to an FP64 accumulator.
 template <int R, bool MIXED>
 __device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
-                                          double4 *s_pos, double4 *s_w64,
-                                          float4 *s_w32) {
+                                          typename PairView<MIXED>::T4 *s_pos,
+                                          typename PairView<MIXED>::T4 *s_w) {
+    using V = PairView<MIXED>;
+    using T = typename V::T;
+    using T4 = typename V::T4;
     const int n = M.n;
     const int tid = threadIdx.x;
     const int row0 = rb * kBlock * R;
     const int row_end = min(n, row0 + kBlock * R);
-    const int tps = MIXED ? M.tps32 : M.tps64;
+    const int tps = V::tps(M);
+    const T4 *pos = V::pos(M), *nrm = V::nrm(M), *wgt = V::wgt(M);
 
-    double tx[R], ty[R], tz[R];
-    double tnx[R], tny[R], tnz[R];
-    float fnx[R], fny[R], fnz[R];
+    T tx[R], ty[R], tz[R], tnx[R], tny[R], tnz[R];
     double top[R], bot[R];
     int ti[R];
 #pragma unroll
@@ -89,26 +135,16 @@ __device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
         const int i = row0 + r * kBlock + tid;
         ti[r] = i;
         const int ic = min(i, n - 1);
-        const double4 p = M.pos[ic];
+        const T4 p = pos[ic], q = nrm[ic];
         tx[r] = p.x;
         ty[r] = p.y;
         tz[r] = p.z;
-        if constexpr (MIXED) {
-            const float4 q = M.nrm32[ic];
-            fnx[r] = q.x;
-            fny[r] = q.y;
-            fnz[r] = q.z;
-        } else {
-            const double4 q = M.nrm[ic];
-            tnx[r] = q.x;
-            tny[r] = q.y;
-            tnz[r] = q.z;
-        }
+        tnx[r] = q.x;
+        tny[r] = q.y;
+        tnz[r] = q.z;
         top[r] = 0.0;
         bot[r] = 0.0;
     }
-    const PairConstF64 c64{M.kappa, M.eps, M.inv_eps};
-    const PairConstF32 c32{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
 
     const int j_begin = sp * tps * kTile;
     for (int tile = 0; tile < tps; ++tile) {
@@ -117,69 +153,50 @@ __device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
         const int cnt = min(kTile, n - jt);
         __syncthreads();
         if (tid < cnt) {
-            s_pos[tid] = M.pos[jt + tid];
-            if constexpr (MIXED)
-                s_w32[tid] = M.wgt32[jt + tid];
-            else
-                s_w64[tid] = M.wgt[jt + tid];
+            s_pos[tid] = pos[jt + tid];
+            s_w[tid] = wgt[jt + tid];
         }
         __syncthreads();
         const bool diag = (jt < row_end) && (jt + cnt > row0);
-        if constexpr (MIXED) {
-            float t32[R], b32[R];
+        T st[R], sb[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) t32[r] = b32[r] = 0.0f;
-            if (!diag) {
-#pragma unroll 2
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const double4 p = s_pos[jj];
-                    const float4 w = s_w32[jj];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        pair_f32(c32, tx[r], ty[r], tz[r], fnx[r], fny[r],
-                                 fnz[r], p.x, p.y, p.z, w.x, w.y, w.z, w.w,
-                                 t32[r], b32[r]);
-                }
+        for (int r = 0; r < R; ++r) {
+            if constexpr (MIXED) {
+                st[r] = sb[r] = T(0);
             } else {
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const double4 p = s_pos[jj];
-                    const float4 w = s_w32[jj];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (jt + jj != ti[r])
-                            pair_f32(c32, tx[r], ty[r], tz[r], fnx[r], fny[r],
-                                     fnz[r], p.x, p.y, p.z, w.x, w.y, w.z,
-                                     w.w, t32[r], b32[r]);
-                }
+                st[r] = top[r];
+                sb[r] = bot[r];
             }
+        }
+        if (!diag) {
+#pragma unroll 2
+            for (int jj = 0; jj < cnt; ++jj) {
+                const T4 p = s_pos[jj];
+                const T4 w = s_w[jj];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                top[r] += (double)t32[r];
-                bot[r] += (double)b32[r];
+                for (int r = 0; r < R; ++r)
+                    pair_eval<MIXED>(M, tx[r], ty[r], tz[r], tnx[r], tny[r], tnz[r], p, w,
+                                     st[r], sb[r]);
             }
         } else {
-            if (!diag) {
-#pragma unroll 2
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const double4 p = s_pos[jj];
-                    const double4 w = s_w64[jj];
+            for (int jj = 0; jj < cnt; ++jj) {
+                const T4 p = s_pos[jj];
+                const T4 w = s_w[jj];
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        pair_f64(c64, tx[r], ty[r], tz[r], tnx[r], tny[r],
-                                 tnz[r], p.x, p.y, p.z, w.x, w.y, w.z, w.w,
-                                 top[r], bot[r]);
-                }
+                for (int r = 0; r < R; ++r)
+                    if (jt + jj != ti[r])
+                        pair_eval<MIXED>(M, tx[r], ty[r], tz[r], tnx[r], tny[r], tnz[r], p,
+                                         w, st[r], sb[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (MIXED) {
+                top[r] += (double)st[r];
+                bot[r] += (double)sb[r];
             } else {
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const double4 p = s_pos[jj];
-                    const double4 w = s_w64[jj];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (jt + jj != ti[r])
-                            pair_f64(c64, tx[r], ty[r], tz[r], tnx[r], tny[r],
-                                     tnz[r], p.x, p.y, p.z, w.x, w.y, w.z,
-                                     w.w, top[r], bot[r]);
-                }
+                top[r] = st[r];
+                bot[r] = sb[r];
             }
         }
     }
@@ -203,9 +220,9 @@ template <bool MIXED, int R>
 __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
     const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
     int *__restrict__ counter, int persistent, int skip) {
-    __shared__ double4 s_pos[kTile];
-    __shared__ double4 s_w64[MIXED ? 1 : kTile];
-    __shared__ float4 s_w32[MIXED ? kTile : 1];
+    using T4 = typename PairView<MIXED>::T4;
+    __shared__ T4 s_pos[kTile];
+    __shared__ T4 s_w[kTile];
     __shared__ int s_next;
     int t = blockIdx.x;
     for (;;) {
@@ -218,7 +235,7 @@ __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
         if (t >= ntiles) break;
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
-        if (!(skip && M.st->done)) pair_tile<R, MIXED>(M, tile.y, tile.z, s_pos, s_w64, s_w32);
+        if (!(skip && M.st->done)) pair_tile<R, MIXED>(M, tile.y, tile.z, s_pos, s_w);
         if (!persistent) break;
     }
 }

@@ -72,6 +72,12 @@ struct PairConstF64 {
     double kappa, eps, inv_eps;
 };
 
+// Both precisions evaluate the row sums in the factored form
+//   top += rinv [ (1-E) s + (eps A - 1) w rinv^2 ]
+//   bot += rinv^3 [ u_x ((A/eps - 1) s - (B-3) w rinv^2) + (A-1) q_n ]
+// with w = r . m_j and q_n = nu_x . m_j; (1-E) s, (A-1) q_n and B-3 are each
+// formed by one fused multiply-add, so at kappa = 0 (E = A = 1, B = 3) the
+// K1 and K4 contributions vanish exactly.
 __device__ __forceinline__ void pair_f64(
     const PairConstF64 &c, double tx, double ty, double tz, double tnx,
     double tny, double tnz, double sx, double sy, double sz, double s,
@@ -79,62 +85,55 @@ __device__ __forceinline__ void pair_f64(
     const double dx = tx - sx, dy = ty - sy, dz = tz - sz;
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
     const double rinv = rsqrt_f64(r2);
-    const double rho = r2 * rinv;
     const double rinv2 = rinv * rinv;
     const double rinv3 = rinv2 * rinv;
-    const double tau = c.kappa * rho;
+    const double tau = c.kappa * (r2 * rinv);
     const double E = exp_neg_f64(tau);
-    const double A = __builtin_fma(E, tau, E);                        // E(1+tau)
-    const double B = E * __builtin_fma(tau, tau + 3.0, 3.0);          // E(3+3tau+tau^2)
+    const double A = __builtin_fma(E, tau, E);                                  // E(1+tau)
+    const double B3 = __builtin_fma(E, __builtin_fma(tau, tau + 3.0, 3.0), -3.0);  // B - 3
     const double ux = __builtin_fma(dx, tnx, __builtin_fma(dy, tny, dz * tnz));
     const double w = __builtin_fma(dx, mx, __builtin_fma(dy, my, dz * mz));
     const double qn = __builtin_fma(tnx, mx, __builtin_fma(tny, my, tnz * mz));
-    // top += (1-E) rinv s + (eps A - 1) rinv3 w
-    const double k1s = __builtin_fma(-E, s, s) * rinv;
-    top += __builtin_fma(__builtin_fma(c.eps, A, -1.0) * rinv3, w, k1s);
-    // bot += (A/eps - 1) ux rinv3 s + (A-1) rinv3 qn - (B-3) rinv2 rinv3 ux w
-    const double uxr3 = ux * rinv3;
-    const double t3 = __builtin_fma(A, c.inv_eps, -1.0) * uxr3 * s;
-    const double t4a = (A - 1.0) * rinv3 * qn;
-    const double t4b = (B - 3.0) * uxr3 * rinv2 * w;
-    bot += (t3 + t4a) - t4b;
+    const double k1 = __builtin_fma(-E, s, s);                                  // (1-E) s
+    const double k2 = __builtin_fma(c.eps, A, -1.0) * w;                        // (eps A-1) w
+    top = __builtin_fma(__builtin_fma(k2, rinv2, k1), rinv, top);
+    const double k3 = __builtin_fma(__builtin_fma(A, c.inv_eps, -1.0), s, -(B3 * rinv2) * w);
+    const double k4 = __builtin_fma(A, qn, -qn);                                // (A-1) q_n
+    bot = __builtin_fma(__builtin_fma(ux, k3, k4), rinv3, bot);
 }
 
 // ---------------------------------------------------------------------------
-// FP32 pair (the mixed product): the separation r is formed in FP64 from
-// FP64 centroids and rounded once to FP32, so near pairs keep full FP32
-// relative accuracy; everything after that is FP32 with the hardware
-// exp2 and reciprocal-square-root instructions.
+// FP32 pair (the mixed product): coordinates relative to the molecule's
+// bounding-box centre rounded once to FP32, the same factored form in FP32
+// with the hardware exp2 and reciprocal-square-root instructions.
 // ---------------------------------------------------------------------------
 struct PairConstF32 {
     float kappa, neg_kappa_log2e, eps, inv_eps;
 };
 
 __device__ __forceinline__ void pair_f32(
-    const PairConstF32 &c, double tx, double ty, double tz, float tnx,
-    float tny, float tnz, double sx, double sy, double sz, float s, float mx,
+    const PairConstF32 &c, float tx, float ty, float tz, float tnx,
+    float tny, float tnz, float sx, float sy, float sz, float s, float mx,
     float my, float mz, float &top, float &bot) {
-    const float dx = (float)(tx - sx), dy = (float)(ty - sy),
-                dz = (float)(tz - sz);
+    const float dx = tx - sx, dy = ty - sy, dz = tz - sz;
     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
     const float rinv = __builtin_amdgcn_rsqf(r2);
-    const float rho = r2 * rinv;
     const float rinv2 = rinv * rinv;
     const float rinv3 = rinv2 * rinv;
+    const float rho = r2 * rinv;
     const float tau = c.kappa * rho;
     const float E = __builtin_amdgcn_exp2f(rho * c.neg_kappa_log2e);
     const float A = __builtin_fmaf(E, tau, E);
-    const float B = E * __builtin_fmaf(tau, tau + 3.0f, 3.0f);
+    const float B3 = __builtin_fmaf(E, __builtin_fmaf(tau, tau + 3.0f, 3.0f), -3.0f);
     const float ux = __builtin_fmaf(dx, tnx, __builtin_fmaf(dy, tny, dz * tnz));
     const float w = __builtin_fmaf(dx, mx, __builtin_fmaf(dy, my, dz * mz));
     const float qn = __builtin_fmaf(tnx, mx, __builtin_fmaf(tny, my, tnz * mz));
-    const float k1s = __builtin_fmaf(-E, s, s) * rinv;
-    top += __builtin_fmaf(__builtin_fmaf(c.eps, A, -1.0f) * rinv3, w, k1s);
-    const float uxr3 = ux * rinv3;
-    const float t3 = __builtin_fmaf(A, c.inv_eps, -1.0f) * uxr3 * s;
-    const float t4a = (A - 1.0f) * rinv3 * qn;
-    const float t4b = (B - 3.0f) * uxr3 * rinv2 * w;
-    bot += (t3 + t4a) - t4b;
+    const float k1 = __builtin_fmaf(-E, s, s);
+    const float k2 = __builtin_fmaf(c.eps, A, -1.0f) * w;
+    top = __builtin_fmaf(__builtin_fmaf(k2, rinv2, k1), rinv, top);
+    const float k3 = __builtin_fmaf(__builtin_fmaf(A, c.inv_eps, -1.0f), s, -(B3 * rinv2) * w);
+    const float k4 = __builtin_fmaf(A, qn, -qn);
+    bot = __builtin_fmaf(__builtin_fmaf(ux, k3, k4), rinv3, bot);
 }
 
 }  // namespace gabi

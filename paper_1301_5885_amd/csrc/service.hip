@@ -40,7 +40,7 @@ double now_s() {
 struct Staged {
     int64_t n = 0, nc = 0;
     std::vector<double4> pos, nrm;
-    std::vector<float4> nrm32;
+    std::vector<float4> geo32;
     std::vector<double> chg;  // 4 nc
     double eps1 = 1, eps2 = 80, kappa = 0;
     double *u_out = nullptr;
@@ -61,7 +61,7 @@ int stage_problem(const gabi_problem &p, int m, Staged &out, std::string &err) {
     }
     out.n = p.n;
     out.nc = p.nc;
-    stage_surface(p.n, p.cx, p.cy, p.cz, p.nx, p.ny, p.nz, p.area, out.pos, out.nrm, out.nrm32);
+    stage_surface(p.n, p.cx, p.cy, p.cz, p.nx, p.ny, p.nz, p.area, out.pos, out.nrm, out.geo32);
     out.chg.resize((size_t)(4 * p.nc));
     for (int64_t k = 0; k < p.nc; ++k) {
         out.chg[4 * k] = p.px[k];
@@ -180,13 +180,14 @@ class HipExecutor : public Executor {
     int admit(Slot &s, const Staged &p, int64_t off, const gabi_solve_opts &o,
               std::string &err) override {
         s.mem = static_cast<char *>(base_) + off;
+        s.uid = next_slot_uid();
         s.mol = Mol{};
         slot_carve(s, p.n, p.nc, o.restart);
         slot_set_params(s, p.eps1, p.eps2, p.kappa);
         slot_set_mode(s, o.mode == GABI_SOLVE_MIXED_IR ? kModeMixed : kModeFP64);
         set_solve_targets(s, o.tol, o.inner_tol, o.maxit);
         s.mol.m = o.restart;
-        if (upload_geometry(s, p.pos.data(), p.nrm.data(), p.nrm32.data(), stream_) ||
+        if (upload_geometry(s, p.pos.data(), p.nrm.data(), p.geo32.data(), stream_) ||
             upload_charges(s, p.chg.data(), stream_)) {
             err = "upload failed";
             return GABI_EDEVICE;
@@ -204,9 +205,12 @@ class HipExecutor : public Executor {
 
     int round(std::vector<Slot *> &active, std::string &err) override {
         if (active.empty()) return GABI_OK;
-        if (active != active_.slots) {
+        std::vector<int64_t> uids;
+        for (const Slot *s : active) uids.push_back(s->uid);
+        if (uids != active_uids_) {
             int rc = use(active_, active, err);
             if (rc) return rc;
+            active_uids_ = uids;
             rounds_since_build_ = 0;
         }
         // capture once the set has been stable for a round
@@ -252,6 +256,7 @@ class HipExecutor : public Executor {
     hipStream_t stream_ = nullptr, capture_ = nullptr;
     void *base_ = nullptr;
     Batch active_, tmp_;
+    std::vector<int64_t> active_uids_;  // slots active_ was built for
     int rounds_since_build_ = 0;
 };
 
@@ -264,6 +269,7 @@ class MockExecutor : public Executor {
     int start(int64_t, std::string &) override { return GABI_OK; }
     int admit(Slot &s, const Staged &p, int64_t, const gabi_solve_opts &o,
               std::string &) override {
+        s.uid = next_slot_uid();
         s.mol = Mol{};
         s.mol.n = (int32_t)p.n;
         s.mol.nc = (int32_t)p.nc;

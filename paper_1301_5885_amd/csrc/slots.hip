@@ -1,6 +1,7 @@
 // Per-molecule device memory (slots), product decomposition and the tuning
 // table it is read from, and batches (block lists over many molecules).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -137,7 +138,8 @@ int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
     Mol t{};
     t.pos = c.take<double4>(n);
     t.nrm = c.take<double4>(n);
-    t.nrm32 = c.take<float4>(n);
+    t.pos32 = c.take<float4>(2 * n);
+    t.nrm32 = t.pos32 ? t.pos32 + n : nullptr;
     t.chg = c.take<double4>(nc);
     t.wgt = c.take<double4>(n);
     t.wgt32 = c.take<float4>(n);
@@ -243,6 +245,11 @@ void set_solve_targets(Slot &slot, double tol, double inner_tol, int maxit) {
     slot.mol.tol0 = tol;
     slot.mol.inner_tol = inner_tol;
     slot.mol.maxit = maxit;
+}
+
+int64_t next_slot_uid() {
+    static std::atomic<int64_t> uid{0};
+    return ++uid;
 }
 
 // ---------------------------------------------------------------- batches

@@ -343,6 +343,18 @@ class Context:
         self.set_charges(p.pos, p.q)
         self.set_params(p.eps1, p.eps2, p.kappa)
 
+    def load_request(self, req):
+        """Surface, charges and parameters of a Request (element arrays)."""
+        self._check(self._lib.gabi_set_surface(self._h, req.n, *[_p(x) for x in req.cols]),
+                    "gabi_set_surface")
+        self.n = req.n
+        self._check(self._lib.gabi_set_charges(self._h, req.nc,
+                                               *[_p(x) if req.nc else None
+                                                 for x in req.charges]),
+                    "gabi_set_charges")
+        self.nc = req.nc
+        self.set_params(req.c.eps1, req.c.eps2, req.c.kappa)
+
     # -- host entry points
     def rhs(self):
         b = np.empty(2 * self.n)

@@ -101,6 +101,39 @@ def test_server_same_alone_and_in_the_mix():
         assert np.array_equal(req.u, u)
 
 
+def test_server_replaced_slot_same_as_alone():
+    """Two slots, one long request and a stream of short ones: every short
+    request takes the place of the one that just finished (the freed slot
+    record is typically handed out again at the same host address), so the
+    running batch must be rebuilt for the newcomer.  Each result equals the
+    request solved alone."""
+    probs = []
+    for k, (nu, R, nc, kappa) in enumerate([(23, 20.0, 150, 0.1), (8, 6.0, 10, 0.2),
+                                            (9, 7.0, 12, 0.0), (8, 6.5, 9, 0.3),
+                                            (10, 7.5, 15, 0.15), (9, 6.0, 11, 0.05)]):
+        rng = np.random.default_rng(300 + k)
+        V, F, shape = star_surface(nu, R, rng)
+        pos = charges_in_star(rng, shape, nc, 0.8)
+        q = rng.normal(0.0, 0.5, nc)
+        probs.append((V, F, pos, q, kappa))
+    log(f"[server slot reuse] N={[len(p[1]) for p in probs]}")
+    ref = alone(probs, tol=1e-8, mode=gabi.SOLVE_MIXED_IR)
+    reqs = requests(probs)
+    with gabi.Server(device=0, budget_bytes=1 << 32, max_slots=2, tol=1e-8,
+                     mode=gabi.SOLVE_MIXED_IR) as s:
+        for r in reqs:
+            s.submit(r)
+        assert s.drain(120.0)
+        res = sorted(s.poll(), key=lambda r: r["tag"])
+        st = s.stats()
+    log(f"    stats {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["max_active"] == 2
+    for (u, E, info), r, req in zip(ref, res, reqs):
+        assert r["status"] == gabi.OK
+        assert r["energy"] == E
+        assert np.array_equal(req.u, u)
+
+
 def test_graph_replay_matches_eager():
     """Rounds replayed from a captured graph give the eager result on every
     replay, with eager work (products) in between."""
