@@ -146,7 +146,7 @@ struct Batch {
     void *d_mem = nullptr;
     int64_t cap_bytes = 0;
     bool persistent = true;
-    int grid64 = 0, grid32 = 0;  // persistent grid sizes
+    int grid64[2] = {0, 0}, grid32[2] = {0, 0};  // persistent grids (R = 2, R = 1)
     // captured round (hipGraph), valid while the batch is unchanged
     hipGraphExec_t graph = nullptr;
     bool graph_valid = false;
@@ -227,7 +227,7 @@ void stage_surface(int64_t n, const double *cx, const double *cy, const double *
 void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);
 void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer *t);
 void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);
-int pair_occupancy_grid(int precision);
+int pair_occupancy_grid(int precision, int rows_index);
 // sources.hip
 void launch_rhs(const Batch &b, hipStream_t s);
 void launch_reaction(const Batch &b, hipStream_t s);

@@ -345,11 +345,11 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
     }
     int *c = b.d_counter + (mixed ? 2 : 0);
     if (mixed) {
-        pair_group<true, 2>(b, s, tiles, cnt[0], c, b.grid32, skip);
-        pair_group<true, 1>(b, s, tiles + cnt[0], cnt[1], c + 1, b.grid32, skip);
+        pair_group<true, 2>(b, s, tiles, cnt[0], c, b.grid32[0], skip);
+        pair_group<true, 1>(b, s, tiles + cnt[0], cnt[1], c + 1, b.grid32[1], skip);
     } else {
-        pair_group<false, 2>(b, s, tiles, cnt[0], c, b.grid64, skip);
-        pair_group<false, 1>(b, s, tiles + cnt[0], cnt[1], c + 1, b.grid64, skip);
+        pair_group<false, 2>(b, s, tiles, cnt[0], c, b.grid64[0], skip);
+        pair_group<false, 1>(b, s, tiles + cnt[0], cnt[1], c + 1, b.grid64[1], skip);
     }
     if (e0 && e1) {
         (void)hipEventRecord(e1, s);
@@ -370,16 +370,25 @@ void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j
                            precision, j, (int)skip);
 }
 
-int pair_occupancy_grid(int precision) {
+template <bool MIXED, int R>
+static int resident_blocks() {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 1024;
-    hipError_t e = precision == GABI_FP64
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<false, 2>, kBlock, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<true, 2>, kBlock, 0);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<MIXED, R>, kBlock, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
     return per_cu * cus;
+}
+
+// Workgroups of the pair kernel (precision, R = 2 - rows_index) resident on
+// the whole device at once: the persistent grid size.
+int pair_occupancy_grid(int precision, int rows_index) {
+    if (precision == GABI_FP64)
+        return rows_index == 0 ? resident_blocks<false, 2>() : resident_blocks<false, 1>();
+    return rows_index == 0 ? resident_blocks<true, 2>() : resident_blocks<true, 1>();
 }
 
 }  // namespace gabi

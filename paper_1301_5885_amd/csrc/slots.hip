@@ -377,13 +377,18 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         return GABI_EDEVICE;
     }
     b.h_status = reinterpret_cast<KrylovStatus *>(h + o_st);
-    static int grid64 = 0, grid32 = 0;
-    if (!grid64) {
-        grid64 = pair_occupancy_grid(GABI_FP64);
-        grid32 = pair_occupancy_grid(GABI_FP32_PAIR);
+    static int grid[2][2] = {{0, 0}, {0, 0}};
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int r = 0; r < 2; ++r) {
+            grid[0][r] = pair_occupancy_grid(GABI_FP64, r);
+            grid[1][r] = pair_occupancy_grid(GABI_FP32_PAIR, r);
+        }
+    });
+    for (int r = 0; r < 2; ++r) {
+        b.grid64[r] = grid[0][r];
+        b.grid32[r] = grid[1][r];
     }
-    b.grid64 = grid64;
-    b.grid32 = grid32;
     return GABI_OK;
 }
 

@@ -30,12 +30,23 @@ from .synth import icosphere
 # One geodesic sphere per N bucket: N = 20 nu^2 (bucket = floor(log2 N)).
 BUCKET_NU = {10: 8, 11: 12, 12: 16, 13: 24, 14: 32, 15: 48, 16: 64, 17: 96, 18: 128}
 ROWS = (1, 2)
-TARGET_BLOCKS = (256, 512, 1024, 2048, 4096, 6144, 8192, 12288, 16384, 24576, 32768, 65536)
+TARGET_BLOCKS = (256, 512, 1024, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576, 32768,
+                 49152, 65536, 98304, 131072, 196608, 262144)
 PRECISIONS = {"fp64": gabi.FP64, "fp32": gabi.FP32_PAIR}
 
 
 def log(*a):
     print(*a, flush=True)
+
+
+def sources_per_split(n, rows_per_thread, target_blocks):
+    """Source tiles per split of the decomposition the library derives from
+    (N, R, target_blocks): candidates with the same (R, result) are the same
+    launch and are timed once."""
+    row_blocks = -(-n // (256 * rows_per_thread))
+    tiles = -(-n // 256)
+    want = max(1, -(-target_blocks // row_blocks))
+    return max(1, -(-tiles // want))
 
 
 def time_product(V, F, precision, reps):
@@ -80,9 +91,13 @@ def tune(buckets, reps, out_path):
         assert int(np.floor(np.log2(n))) == b
         for key, prec in PRECISIONS.items():
             default = gabi.tune_get(prec, b)
-            rows = []
+            rows, seen = [], set()
             for R in ROWS:
                 for tb in TARGET_BLOCKS:
+                    key_rt = (R, sources_per_split(n, R, tb))
+                    if key_rt in seen:
+                        continue
+                    seen.add(key_rt)
                     gabi.tune_set(prec, b, R, tb)
                     ms = time_product(V, F, prec, reps)
                     rows.append((ms, R, tb))
