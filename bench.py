@@ -136,12 +136,12 @@ def roofline(res, key, n, workload, gabi=None):
     peak = PEAK_TFLOPS[key]
     t = traffic_from_profiles(f"pair_{key}", workload)
     bucket = n.bit_length() - 1
-    R, blocks = gabi.tune_get(gabi.FP32_PAIR if key == "fp32" else gabi.FP64, bucket)
+    R, blocks, tail = gabi.tune_get(gabi.FP32_PAIR if key == "fp32" else gabi.FP64, bucket)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": t,
             "kernel": f"gabi::pair_kernel<{'true' if key == 'fp32' else 'false'}, {R}>",
-            "target_blocks": blocks,
+            "target_blocks": blocks, "tail_pieces": tail,
             "avg_launch_ms": round(avg_s * 1e3, 5),
             "flop_per_launch": flop}
 

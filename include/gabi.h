@@ -202,15 +202,21 @@ int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
 /* ------------------------------------------------------------------------ */
 
 /* A product of N elements is split into row blocks of 256 * rows_per_thread
- * targets and into source splits so that about target_blocks workgroups
- * run (the split partials are added in split order).  The table holds one
- * (rows_per_thread, target_blocks) per precision and N bucket
- * (bucket = floor(log2 N), 0..39).  The decomposition fixes the summation
- * order, so set the table before creating contexts or servers: every solve
- * made under one table is bitwise reproducible.  rows_per_thread is 1 or 2;
- * target_blocks in [1, 2^20].  GABI_EINVAL otherwise.                       */
-int gabi_tune_set(int precision, int bucket, int rows_per_thread, int target_blocks);
-int gabi_tune_get(int precision, int bucket, int *rows_per_thread, int *target_blocks);
+ * targets and into source splits: the last tail_pieces * 64 sources form
+ * splits of 64 sources each, the sources before them splits of whole
+ * 256-source tiles sized so that about target_blocks workgroups run.  The
+ * work items (row block, split) are taken longest first, so the short tail
+ * splits fill the last round of the device.  A row's split partials are
+ * added in source order.  The table holds one entry per precision and N
+ * bucket (bucket = floor(log2 N), 0..39).  The decomposition fixes the
+ * summation order, so set the table before creating contexts or servers:
+ * every solve made under one table is bitwise reproducible, alone or
+ * batched.  rows_per_thread is 1 or 2; target_blocks in [1, 2^20];
+ * tail_pieces in [0, 4096].  GABI_EINVAL otherwise.                          */
+int gabi_tune_set(int precision, int bucket, int rows_per_thread, int target_blocks,
+                  int tail_pieces);
+int gabi_tune_get(int precision, int bucket, int *rows_per_thread, int *target_blocks,
+                  int *tail_pieces);
 
 /* ------------------------------------------------------------------------ */
 /* Many molecules at once.                                                  */

@@ -18,6 +18,7 @@ namespace gabi {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kTile = 256;           // sources staged in LDS per tile
+constexpr int kPiece = 64;           // sources of one tail split
 constexpr int kBlasBlocksMax = 256;  // workgroups per molecule in reductions
 constexpr int kMaxRestart = 64;
 constexpr double kPi = 3.14159265358979323846;
@@ -26,17 +27,34 @@ constexpr double kCoulomb = 332.0716;  // kcal A / (mol e^2)
 // ---------------------------------------------------------------------------
 // Decomposition of one product: row blocks x source splits.  A function of
 // N and the precision (and the loaded tuning table) only.
+// Sources [0, tail_start) form `head` splits of tiles_per_split tiles of 256;
+// [tail_start, N) forms splits of kPiece sources.
 struct PairLaunch {
     int rows_per_thread = 1;
     int row_blocks = 0;
     int tiles_per_split = 0;
     int splits = 0;
+    int head = 0;
+    int tail_start = 0;
 };
 
 struct TuneEntry {  // one row of the tuning table
     int rows_per_thread = 2;
     int target_blocks = 2048;
+    int tail_pieces = 0;
 };
+
+// Source range [begin, end) of split sp.
+__host__ __device__ inline void split_range(int n, int tps, int head, int tail_start, int sp,
+                                            int &begin, int &end) {
+    if (sp < head) {
+        begin = sp * tps * kTile;
+        end = begin + tps * kTile < tail_start ? begin + tps * kTile : tail_start;
+    } else {
+        begin = tail_start + (sp - head) * kPiece;
+        end = begin + kPiece < n ? begin + kPiece : n;
+    }
+}
 
 PairLaunch pair_launch(int64_t n, int precision);
 int blas_blocks(int64_t n);
@@ -72,6 +90,7 @@ struct Mol {
     int32_t mode;
     int32_t R64, rb64, tps64, sp64;   // FP64 product decomposition
     int32_t R32, rb32, tps32, sp32;   // FP32-pair product decomposition
+    int32_t head64, tail64, head32, tail32;  // split source ranges (split_range)
     int32_t rx_kblocks, rx_tps, rx_splits, maxit;
     double kappa, eps, inv_eps, d_top, d_bot, rhs_scale;
     double tol0, inner_tol;             // solve targets (copied into st)

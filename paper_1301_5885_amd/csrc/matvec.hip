@@ -80,6 +80,8 @@ template <> struct PairView<false> {
     static __device__ __forceinline__ const T4 *nrm(const Mol &M) { return M.nrm; }
     static __device__ __forceinline__ const T4 *wgt(const Mol &M) { return M.wgt; }
     static __device__ __forceinline__ int tps(const Mol &M) { return M.tps64; }
+    static __device__ __forceinline__ int head(const Mol &M) { return M.head64; }
+    static __device__ __forceinline__ int tail(const Mol &M) { return M.tail64; }
 };
 template <> struct PairView<true> {
     using T = float;
@@ -88,6 +90,8 @@ template <> struct PairView<true> {
     static __device__ __forceinline__ const T4 *nrm(const Mol &M) { return M.nrm32; }
     static __device__ __forceinline__ const T4 *wgt(const Mol &M) { return M.wgt32; }
     static __device__ __forceinline__ int tps(const Mol &M) { return M.tps32; }
+    static __device__ __forceinline__ int head(const Mol &M) { return M.head32; }
+    static __device__ __forceinline__ int tail(const Mol &M) { return M.tail32; }
 };
 
 template <bool MIXED>
@@ -124,7 +128,8 @@ __device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
     const int tid = threadIdx.x;
     const int row0 = rb * kBlock * R;
     const int row_end = min(n, row0 + kBlock * R);
-    const int tps = V::tps(M);
+    int j_begin, j_end;
+    split_range(n, V::tps(M), V::head(M), V::tail(M), sp, j_begin, j_end);
     const T4 *pos = V::pos(M), *nrm = V::nrm(M), *wgt = V::wgt(M);
 
     T tx[R], ty[R], tz[R], tnx[R], tny[R], tnz[R];
@@ -146,11 +151,8 @@ __device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
         bot[r] = 0.0;
     }
 
-    const int j_begin = sp * tps * kTile;
-    for (int tile = 0; tile < tps; ++tile) {
-        const int jt = j_begin + tile * kTile;
-        if (jt >= n) break;
-        const int cnt = min(kTile, n - jt);
+    for (int jt = j_begin; jt < j_end; jt += kTile) {
+        const int cnt = min(kTile, j_end - jt);
         __syncthreads();
         if (tid < cnt) {
             s_pos[tid] = pos[jt + tid];

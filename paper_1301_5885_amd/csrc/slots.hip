@@ -46,6 +46,7 @@ int set_tune_entry(int precision, int bucket, TuneEntry e) {
     if (bucket < 0 || bucket >= kBuckets) return GABI_EINVAL;
     if (e.rows_per_thread != 1 && e.rows_per_thread != 2) return GABI_EINVAL;
     if (e.target_blocks < 1 || e.target_blocks > (1 << 20)) return GABI_EINVAL;
+    if (e.tail_pieces < 0 || e.tail_pieces > 4096) return GABI_EINVAL;
     std::lock_guard<std::mutex> lk(g_table_mu);
     init_table_locked();
     g_table[precision == GABI_FP64 ? 0 : 1][bucket] = e;
@@ -64,34 +65,42 @@ PairLaunch pair_launch(int64_t n, int precision) {
     L.rows_per_thread = e.rows_per_thread;
     const int64_t rows_per_block = (int64_t)kBlock * L.rows_per_thread;
     L.row_blocks = (int)((n + rows_per_block - 1) / rows_per_block);
-    const int64_t tiles = (n + kTile - 1) / kTile;
+    // the tail: the last tail_pieces pieces of kPiece sources (aligned to kPiece)
+    const int64_t pieces = (n + kPiece - 1) / kPiece;
+    const int64_t tail_start =
+        std::min<int64_t>(n, std::max<int64_t>(0, pieces - e.tail_pieces) * kPiece);
+    L.tail_start = (int)tail_start;
+    const int64_t tiles = (tail_start + kTile - 1) / kTile;
     int64_t want = (e.target_blocks + L.row_blocks - 1) / L.row_blocks;
     if (want < 1) want = 1;
     int64_t tps = (tiles + want - 1) / want;
     if (tps < 1) tps = 1;
     L.tiles_per_split = (int)tps;
-    L.splits = (int)((tiles + tps - 1) / tps);
+    L.head = (int)((tiles + tps - 1) / tps);
+    L.splits = L.head + (int)((n - tail_start + kPiece - 1) / kPiece);
     return L;
 }
 
 }  // namespace gabi
 
 extern "C" int gabi_tune_set(int precision, int bucket, int rows_per_thread,
-                             int target_blocks) {
+                             int target_blocks, int tail_pieces) {
     if (precision != GABI_FP64 && precision != GABI_FP32_PAIR) return GABI_EINVAL;
     gabi::TuneEntry e;
     e.rows_per_thread = rows_per_thread;
     e.target_blocks = target_blocks;
+    e.tail_pieces = tail_pieces;
     return gabi::set_tune_entry(precision, bucket, e);
 }
 
 extern "C" int gabi_tune_get(int precision, int bucket, int *rows_per_thread,
-                             int *target_blocks) {
+                             int *target_blocks, int *tail_pieces) {
     if ((precision != GABI_FP64 && precision != GABI_FP32_PAIR) || bucket < 0 || bucket >= 40)
         return GABI_EINVAL;
     const gabi::TuneEntry e = gabi::tune_entry(precision, int64_t(1) << bucket);
     if (rows_per_thread) *rows_per_thread = e.rows_per_thread;
     if (target_blocks) *target_blocks = e.target_blocks;
+    if (tail_pieces) *tail_pieces = e.tail_pieces;
     return GABI_OK;
 }
 
@@ -176,6 +185,10 @@ int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
         t.rb32 = L32.row_blocks;
         t.tps32 = L32.tiles_per_split;
         t.sp32 = L32.splits;
+        t.head64 = L64.head;
+        t.tail64 = L64.tail_start;
+        t.head32 = L32.head;
+        t.tail32 = L32.tail_start;
         t.rx_kblocks = kb;
         t.rx_tps = tps;
         t.rx_splits = sp;
@@ -279,10 +292,17 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         const int eb = (M.n + kBlock - 1) / kBlock;
         for (int i = 0; i < eb; ++i) elem.push_back(make_int2(k, i));
         for (int i = 0; i < M.nb; ++i) blas.push_back(make_int2(k, i));
-        for (int sp = 0; sp < M.sp64; ++sp)
-            for (int rb = 0; rb < M.rb64; ++rb) t64.push_back(make_int4(k, rb, sp, M.R64 * M.tps64));
-        for (int sp = 0; sp < M.sp32; ++sp)
-            for (int rb = 0; rb < M.rb32; ++rb) t32.push_back(make_int4(k, rb, sp, M.R32 * M.tps32));
+        // (mol, row block, split, cost = rows per thread x sources)
+        for (int sp = 0; sp < M.sp64; ++sp) {
+            int j0, j1;
+            split_range(M.n, M.tps64, M.head64, M.tail64, sp, j0, j1);
+            for (int rb = 0; rb < M.rb64; ++rb) t64.push_back(make_int4(k, rb, sp, M.R64 * (j1 - j0)));
+        }
+        for (int sp = 0; sp < M.sp32; ++sp) {
+            int j0, j1;
+            split_range(M.n, M.tps32, M.head32, M.tail32, sp, j0, j1);
+            for (int rb = 0; rb < M.rb32; ++rb) t32.push_back(make_int4(k, rb, sp, M.R32 * (j1 - j0)));
+        }
         if (M.nc > 0)
             for (int sp = 0; sp < M.rx_splits; ++sp)
                 for (int kb = 0; kb < M.rx_kblocks; ++kb) rx.push_back(make_int4(k, kb, sp, 0));

@@ -146,8 +146,8 @@ def load():
     lib.gabi_device_bytes.restype = C.c_int64
     lib.gabi_set_kernel_timing.argtypes = [ctx, C.c_int]
     lib.gabi_kernel_time.argtypes = [ctx, C.c_int, _dp, C.POINTER(C.c_int64), C.c_int]
-    lib.gabi_tune_set.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
-    lib.gabi_tune_get.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.gabi_tune_set.argtypes = [C.c_int] * 5
+    lib.gabi_tune_get.argtypes = [C.c_int, C.c_int] + [C.POINTER(C.c_int)] * 3
     lib.gabi_solve_footprint.argtypes = [_i64, _i64, C.c_int32]
     lib.gabi_solve_footprint.restype = C.c_int64
     lib.gabi_batch_solve.argtypes = [C.c_int, _i64, C.POINTER(ProblemC),
@@ -185,24 +185,25 @@ def _apply_tuning(lib):
     for key, prec in (("fp64", FP64), ("fp32", FP32_PAIR)):
         for bucket, e in table.get("entries", {}).get(key, {}).items():
             rc = lib.gabi_tune_set(prec, int(bucket), int(e["rows_per_thread"]),
-                                   int(e["target_blocks"]))
+                                   int(e["target_blocks"]), int(e.get("tail_pieces", 0)))
             if rc != OK:
                 raise GabiError(rc, f"bad tuning entry {key}/{bucket} in {path}")
 
 
-def tune_set(precision, bucket, rows_per_thread, target_blocks):
+def tune_set(precision, bucket, rows_per_thread, target_blocks, tail_pieces=0):
     rc = load().gabi_tune_set(int(precision), int(bucket), int(rows_per_thread),
-                              int(target_blocks))
+                              int(target_blocks), int(tail_pieces))
     if rc != OK:
         raise GabiError(rc, "gabi_tune_set")
 
 
 def tune_get(precision, bucket):
-    r, t = C.c_int(), C.c_int()
-    rc = load().gabi_tune_get(int(precision), int(bucket), C.byref(r), C.byref(t))
+    """(rows_per_thread, target_blocks, tail_pieces) of a table entry."""
+    r, t, p = C.c_int(), C.c_int(), C.c_int()
+    rc = load().gabi_tune_get(int(precision), int(bucket), C.byref(r), C.byref(t), C.byref(p))
     if rc != OK:
         raise GabiError(rc, "gabi_tune_get")
-    return r.value, t.value
+    return r.value, t.value, p.value
 
 
 def _f64(a):

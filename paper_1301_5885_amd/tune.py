@@ -2,13 +2,16 @@
 
 The product of one molecule (the double sum over targets i and sources j of
 the K1..K4 pair kernels, eqs. (eqdbef1)/(eqdbef2)) is cut into row blocks of
-256 * R targets and into source splits so that about `target_blocks`
-workgroups run; a persistent grid drains the resulting tile list.  This
-module times the whole product (pair kernel plus the ordered split
-reduction) for every candidate (R, target_blocks) on geodesic spheres of one
-representative size per N bucket (bucket = floor(log2 N)), for both pair
-precisions, and writes the fastest entry per bucket as JSON.  The library
-applies that table when it is loaded (`gabi.TUNING_PATH`).
+256 * R targets and into source splits: whole 256-source tiles sized so that
+about `target_blocks` workgroups run, then `tail_pieces` splits of 64
+sources at the end of the source range; a persistent grid drains the
+resulting list longest first, so the short tail splits fill the device's
+last round.  This module times the whole product (pair kernel plus the
+ordered split reduction) on geodesic spheres of one representative size per
+N bucket (bucket = floor(log2 N)), for both pair precisions: first every
+(R, target_blocks) without a tail, then the three fastest of those with
+each tail length, and writes the fastest entry per bucket as JSON.  The
+library applies that table when it is loaded (`gabi.TUNING_PATH`).
 
 The decomposition fixes the order of the row sums, so a table change
 changes results in the last bits; every result made under one table is
@@ -32,6 +35,7 @@ BUCKET_NU = {10: 8, 11: 12, 12: 16, 13: 24, 14: 32, 15: 48, 16: 64, 17: 96, 18: 
 ROWS = (1, 2)
 TARGET_BLOCKS = (256, 512, 1024, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576, 32768,
                  49152, 65536, 98304, 131072, 196608, 262144)
+TAILS = (4, 8, 16, 32, 64, 128)
 PRECISIONS = {"fp64": gabi.FP64, "fp32": gabi.FP32_PAIR}
 
 
@@ -41,8 +45,8 @@ def log(*a):
 
 def sources_per_split(n, rows_per_thread, target_blocks):
     """Source tiles per split of the decomposition the library derives from
-    (N, R, target_blocks): candidates with the same (R, result) are the same
-    launch and are timed once."""
+    (N, R, target_blocks) without a tail: candidates with the same (R, result)
+    are the same launch and are timed once."""
     row_blocks = -(-n // (256 * rows_per_thread))
     tiles = -(-n // 256)
     want = max(1, -(-target_blocks // row_blocks))
@@ -81,7 +85,8 @@ def tune(buckets, reps, out_path):
         raise RuntimeError("the autotuner needs a GPU")
     gabi.load()
     table = {"device": torch.cuda.get_device_name(0), "reps": reps,
-             "candidates": {"rows_per_thread": list(ROWS), "target_blocks": list(TARGET_BLOCKS)},
+             "candidates": {"rows_per_thread": list(ROWS), "target_blocks": list(TARGET_BLOCKS),
+                            "tail_pieces": [0] + list(TAILS)},
              "entries": {k: {} for k in PRECISIONS}, "sweep": {k: {} for k in PRECISIONS}}
     t_start = time.time()
     for b in buckets:
@@ -98,20 +103,29 @@ def tune(buckets, reps, out_path):
                     if key_rt in seen:
                         continue
                     seen.add(key_rt)
-                    gabi.tune_set(prec, b, R, tb)
+                    gabi.tune_set(prec, b, R, tb, 0)
                     ms = time_product(V, F, prec, reps)
-                    rows.append((ms, R, tb))
+                    rows.append((ms, R, tb, 0))
+            rows.sort()
+            untailed = rows[0]
+            for _, R, tb, _ in rows[:3]:
+                for tail in TAILS:
+                    if tail * 64 >= n // 2:
+                        continue
+                    gabi.tune_set(prec, b, R, tb, tail)
+                    ms = time_product(V, F, prec, reps)
+                    rows.append((ms, R, tb, tail))
             gabi.tune_set(prec, b, *default)
             rows.sort()
-            ms, R, tb = rows[0]
+            ms, R, tb, tail = rows[0]
             pairs = n * (n - 1)
             table["entries"][key][str(b)] = {"rows_per_thread": R, "target_blocks": tb,
-                                             "n": n, "ms": round(ms, 5),
+                                             "tail_pieces": tail, "n": n, "ms": round(ms, 5),
                                              "gpairs_per_s": round(pairs / ms / 1e6, 2)}
-            table["sweep"][key][str(b)] = [[R, tb, round(m, 5)] for m, R, tb in rows]
-            log(f"bucket {b:2d} N={n:7d} {key}: best R={R} blocks={tb:5d} {ms:9.4f} ms "
-                f"({pairs / ms / 1e6:8.1f} Gpairs/s); worst {rows[-1][0]:.4f} ms "
-                f"[{time.time() - t_start:.0f} s]")
+            table["sweep"][key][str(b)] = [[R, tb, t, round(m, 5)] for m, R, tb, t in rows]
+            log(f"bucket {b:2d} N={n:7d} {key}: best R={R} blocks={tb:6d} tail={tail:3d} "
+                f"{ms:9.4f} ms ({pairs / ms / 1e6:8.1f} Gpairs/s); best without tail "
+                f"{untailed[0]:.4f} ms; worst {rows[-1][0]:.4f} ms [{time.time() - t_start:.0f} s]")
     with open(out_path + ".tmp", "w") as f:
         json.dump(table, f, indent=1)
     os.replace(out_path + ".tmp", out_path)
