@@ -136,11 +136,15 @@ def roofline(res, key, n, workload, gabi=None):
     peak = PEAK_TFLOPS[key]
     t = traffic_from_profiles(f"pair_{key}", workload)
     bucket = n.bit_length() - 1
-    R, blocks, tail = gabi.tune_get(gabi.FP32_PAIR if key == "fp32" else gabi.FP64, bucket)
+    scheme, R, blocks, tail = gabi.tune_get(gabi.FP32_PAIR if key == "fp32" else gabi.FP64,
+                                            bucket)
+    mixed = "true" if key == "fp32" else "false"
+    kname = (f"gabi::sym_pair_kernel<{mixed}>" if scheme == gabi.SCHEME_SYMMETRIC
+             else f"gabi::pair_kernel<{mixed}, {R}>")
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": t,
-            "kernel": f"gabi::pair_kernel<{'true' if key == 'fp32' else 'false'}, {R}>",
+            "kernel": kname, "scheme": "symmetric" if scheme else "split",
             "target_blocks": blocks, "tail_pieces": tail,
             "avg_launch_ms": round(avg_s * 1e3, 5),
             "flop_per_launch": flop}

@@ -201,22 +201,37 @@ int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
 /* Decomposition of the product (tuning table).                             */
 /* ------------------------------------------------------------------------ */
 
-/* A product of N elements is split into row blocks of 256 * rows_per_thread
- * targets and into source splits: the last tail_pieces * 64 sources form
- * splits of 64 sources each, the sources before them splits of whole
- * 256-source tiles sized so that about target_blocks workgroups run.  The
- * work items (row block, split) are taken longest first, so the short tail
- * splits fill the last round of the device.  A row's split partials are
- * added in source order.  The table holds one entry per precision and N
- * bucket (bucket = floor(log2 N), 0..39).  The decomposition fixes the
- * summation order, so set the table before creating contexts or servers:
- * every solve made under one table is bitwise reproducible, alone or
- * batched.  rows_per_thread is 1 or 2; target_blocks in [1, 2^20];
+/* Two decompositions of the product over targets i and sources j != i:
+ *
+ * GABI_SCHEME_SPLIT      row blocks of 256 * rows_per_thread targets times
+ *                        source splits: the last tail_pieces * 64 sources
+ *                        form splits of 64 sources each, the sources before
+ *                        them splits of whole 256-source tiles sized so that
+ *                        about target_blocks workgroups run.  Every ordered
+ *                        pair (i, j) is evaluated on its own.
+ * GABI_SCHEME_SYMMETRIC  blocks of 256 elements; a workgroup takes a block
+ *                        pair (I, J), I < J, and evaluates each unordered
+ *                        pair once: the separation, 1/rho, e^{-kappa rho}
+ *                        and the A, B factors are shared by the (i, j) and
+ *                        (j, i) terms (K1 is symmetric; K2..K4 differ only
+ *                        in which normal and weights they use).  Diagonal
+ *                        blocks (I, I) evaluate their ordered pairs.  Row
+ *                        partial sums are kept per 256-source block.
+ *                        rows_per_thread must be 1; target_blocks and
+ *                        tail_pieces are not used.
+ *
+ * Work items are taken longest first.  A row's partial sums are added in
+ * source order, and the decomposition depends only on N, the precision and
+ * this table, so set the table before creating contexts or servers: every
+ * solve made under one table is bitwise reproducible, alone or batched.  The
+ * table holds one entry per precision and N bucket (bucket = floor(log2 N),
+ * 0..39).  rows_per_thread is 1 or 2; target_blocks in [1, 2^20];
  * tail_pieces in [0, 4096].  GABI_EINVAL otherwise.                          */
-int gabi_tune_set(int precision, int bucket, int rows_per_thread, int target_blocks,
-                  int tail_pieces);
-int gabi_tune_get(int precision, int bucket, int *rows_per_thread, int *target_blocks,
-                  int *tail_pieces);
+typedef enum { GABI_SCHEME_SPLIT = 0, GABI_SCHEME_SYMMETRIC = 1 } gabi_scheme;
+int gabi_tune_set(int precision, int bucket, int scheme, int rows_per_thread,
+                  int target_blocks, int tail_pieces);
+int gabi_tune_get(int precision, int bucket, int *scheme, int *rows_per_thread,
+                  int *target_blocks, int *tail_pieces);
 
 /* ------------------------------------------------------------------------ */
 /* Many molecules at once.                                                  */

@@ -30,6 +30,7 @@ constexpr double kCoulomb = 332.0716;  // kcal A / (mol e^2)
 // Sources [0, tail_start) form `head` splits of tiles_per_split tiles of 256;
 // [tail_start, N) forms splits of kPiece sources.
 struct PairLaunch {
+    int scheme = GABI_SCHEME_SPLIT;  // symmetric: row_blocks = splits = blocks of 256
     int rows_per_thread = 1;
     int row_blocks = 0;
     int tiles_per_split = 0;
@@ -39,6 +40,7 @@ struct PairLaunch {
 };
 
 struct TuneEntry {  // one row of the tuning table
+    int scheme = GABI_SCHEME_SPLIT;
     int rows_per_thread = 2;
     int target_blocks = 2048;
     int tail_pieces = 0;
@@ -91,6 +93,9 @@ struct Mol {
     int32_t R64, rb64, tps64, sp64;   // FP64 product decomposition
     int32_t R32, rb32, tps32, sp32;   // FP32-pair product decomposition
     int32_t head64, tail64, head32, tail32;  // split source ranges (split_range)
+    // symmetric scheme per precision (then R = 1, rb = sp = nbk blocks of 256,
+    // and the FP32-pair partial sums are stored as float)
+    int32_t sym64, sym32, nbk, pad_sym;
     int32_t rx_kblocks, rx_tps, rx_splits, maxit;
     double kappa, eps, inv_eps, d_top, d_bot, rhs_scale;
     double tol0, inner_tol;             // solve targets (copied into st)
@@ -152,10 +157,11 @@ struct Batch {
     Mol *d_mols = nullptr;
     int2 *d_elem = nullptr;   int n_elem = 0;   // (mol, block) over ceil(n/256)
     int2 *d_blas = nullptr;   int n_blas = 0;   // (mol, block) over nb
-    // product tiles (mol, row block, split, cost), two rows per thread first,
-    // then one row per thread: n_tilesXX[0] and n_tilesXX[1] entries
-    int4 *d_tiles64 = nullptr; int n_tiles64[2] = {0, 0};
-    int4 *d_tiles32 = nullptr; int n_tiles32[2] = {0, 0};
+    // product tiles grouped by kernel variant: split scheme with two rows per
+    // thread (mol, row block, split, cost), then one row per thread, then the
+    // symmetric scheme (mol, block I, block J, cost): n_tilesXX[0..2] entries
+    int4 *d_tiles64 = nullptr; int n_tiles64[3] = {0, 0, 0};
+    int4 *d_tiles32 = nullptr; int n_tiles32[3] = {0, 0, 0};
     int4 *d_rx = nullptr;     int n_rx = 0;     // (mol, charge block, split, 0)
     int *d_counter = nullptr;  // tile queues of the persistent product (4)
     KrylovStatus *d_status = nullptr;  // gathered statuses, one per molecule
@@ -165,7 +171,7 @@ struct Batch {
     void *d_mem = nullptr;
     int64_t cap_bytes = 0;
     bool persistent = true;
-    int grid64[2] = {0, 0}, grid32[2] = {0, 0};  // persistent grids (R = 2, R = 1)
+    int grid64[3] = {0, 0, 0}, grid32[3] = {0, 0, 0};  // persistent grids per variant
     // captured round (hipGraph), valid while the batch is unchanged
     hipGraphExec_t graph = nullptr;
     bool graph_valid = false;
@@ -246,7 +252,7 @@ void stage_surface(int64_t n, const double *cx, const double *cy, const double *
 void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);
 void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer *t);
 void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);
-int pair_occupancy_grid(int precision, int rows_index);
+int pair_occupancy_grid(int precision, int variant);
 // sources.hip
 void launch_rhs(const Batch &b, hipStream_t s);
 void launch_reaction(const Batch &b, hipStream_t s);

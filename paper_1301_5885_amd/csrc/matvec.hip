@@ -242,6 +242,163 @@ __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
     }
 }
 
+// ------------------------------------------------------------- symmetric
+// Tile (I, J) of the symmetric scheme, one element of block I per thread.
+// The workgroup stages block J in LDS (three 4-vectors per element:
+// (x, y, z, s), (nx, ny, nz, mx), (my, mz, -, -)), taken in four chunks of 64
+// elements.  At step s of a chunk lane l reads element (l - s) mod 64, so the
+// 64 lanes of a wave read 64 different elements (no bank conflicts) and meet
+// every element of the chunk once in 64 steps:
+//  * I < J: each unordered pair is evaluated once; the (i, j) terms add to the
+//    lane's own row sums, the (j, i) terms to column sums that rotate through
+//    the wave with the read pattern (DPP wave_ror:1) and are back in their
+//    home lane after 64 steps.  The four waves' column sums of an element are
+//    added in wave order through LDS.  Row sums go to partial slot J of row
+//    i, column sums to slot I of row j.
+//  * I = J: the ordered pairs (i, j), i != j, of the block (row sums only)
+//    go to slot I.
+// Every slot of every row is written by exactly one tile, and the finish adds
+// the slots in block order.  Elements past N (the ragged last block) sit far
+// away (rows and columns on opposite sides) with zero weights, so their terms
+// are exactly zero and every lane takes part in the rotation; their own sums
+// are not stored.
+template <bool MIXED>
+__device__ __forceinline__ SymElem<typename PairView<MIXED>::T> sym_load(const Mol &M, int e,
+                                                                        bool active,
+                                                                        float far) {
+    using V = PairView<MIXED>;
+    using T = typename V::T;
+    const int ec = active ? e : M.n - 1;
+    const typename V::T4 p = V::pos(M)[ec], q = V::nrm(M)[ec], w = V::wgt(M)[ec];
+    SymElem<T> a;
+    a.x = active ? p.x : T(far);
+    a.y = active ? p.y : T(far);
+    a.z = active ? p.z : T(far);
+    a.nx = q.x;
+    a.ny = q.y;
+    a.nz = q.z;
+    a.s = active ? w.x : T(0);
+    a.mx = active ? w.y : T(0);
+    a.my = active ? w.z : T(0);
+    a.mz = active ? w.w : T(0);
+    return a;
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void sym_tile(const Mol &M, int I, int J,
+                                         typename PairView<MIXED>::T4 *s_stage) {
+    using T = typename PairView<MIXED>::T;
+    using T4 = typename PairView<MIXED>::T4;
+    const int n = M.n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = I * kTile + tid;
+    const bool act = i < n;
+    const SymElem<T> a = sym_load<MIXED>(M, i, act, 1e17f);
+    const int jt = J * kTile;
+    const int cnt = min(kTile, n - jt);
+    T4 *sa = s_stage, *sb = s_stage + kTile, *sc = s_stage + 2 * kTile;
+    {
+        const SymElem<T> e = sym_load<MIXED>(M, jt + tid, tid < cnt, -1e17f);
+        sa[tid] = T4{e.x, e.y, e.z, e.s};
+        sb[tid] = T4{e.nx, e.ny, e.nz, e.mx};
+        sc[tid] = T4{e.my, e.mz, T(0), T(0)};
+    }
+    __syncthreads();
+    T *part = reinterpret_cast<T *>(M.part);  // float for the FP32-pair product
+    T top = T(0), bot = T(0);
+    T colt[kTile / 64], colb[kTile / 64];
+#pragma unroll
+    for (int c = 0; c < kTile / 64; ++c) {
+        colt[c] = colb[c] = T(0);
+        if (c * 64 >= cnt) continue;
+        const T4 *ca = sa + c * 64, *cb = sb + c * 64, *cc = sc + c * 64;
+        if (I == J) {
+            for (int s = 0; s < 64; ++s) {
+                const int k = (lane - s) & 63;
+                if (c == wave && s == 0) continue;  // i paired with itself
+                const T4 p = ca[k], q = cb[k], r = cc[k];
+                if constexpr (MIXED) {
+                    const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
+                    pair_f32(kc, a.x, a.y, a.z, a.nx, a.ny, a.nz, p.x, p.y, p.z, p.w, q.w, r.x,
+                             r.y, top, bot);
+                } else {
+                    const PairConstF64 kc{M.kappa, M.eps, M.inv_eps};
+                    pair_f64(kc, a.x, a.y, a.z, a.nx, a.ny, a.nz, p.x, p.y, p.z, p.w, q.w, r.x,
+                             r.y, top, bot);
+                }
+            }
+        } else {
+            T ctop = T(0), cbot = T(0);
+            for (int s = 0; s < 64; ++s) {
+                const int k = (lane - s) & 63;
+                const T4 p = ca[k], q = cb[k], r = cc[k];
+                const SymElem<T> b{p.x, p.y, p.z, q.x, q.y, q.z, p.w, q.w, r.x, r.y};
+                if constexpr (MIXED) {
+                    const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
+                    sym_f32(kc, a, b, top, bot, ctop, cbot);
+                } else {
+                    const PairConstF64 kc{M.kappa, M.eps, M.inv_eps};
+                    sym_f64(kc, a, b, top, bot, ctop, cbot);
+                }
+                ctop = wave_rotate(ctop);
+                cbot = wave_rotate(cbot);
+            }
+            colt[c] = ctop;
+            colb[c] = cbot;
+        }
+    }
+    if (I != J) {
+        // the staging area is free once every wave is past its last chunk
+        T *s_col = reinterpret_cast<T *>(s_stage);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kTile / 64; ++c) {
+            s_col[(2 * wave) * kTile + c * 64 + lane] = colt[c];
+            s_col[(2 * wave + 1) * kTile + c * 64 + lane] = colb[c];
+        }
+        __syncthreads();
+        if (tid < cnt) {
+            T ct = s_col[tid], cbs = s_col[kTile + tid];
+#pragma unroll
+            for (int w = 1; w < kBlock / 64; ++w) {
+                ct += s_col[(2 * w) * kTile + tid];
+                cbs += s_col[(2 * w + 1) * kTile + tid];
+            }
+            part[(size_t)(2 * I) * n + jt + tid] = ct;
+            part[(size_t)(2 * I + 1) * n + jt + tid] = cbs;
+        }
+    }
+    if (act) {
+        part[(size_t)(2 * J) * n + i] = top;
+        part[(size_t)(2 * J + 1) * n + i] = bot;
+    }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void sym_pair_kernel(
+    const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
+    int *__restrict__ counter, int persistent, int skip) {
+    using T4 = typename PairView<MIXED>::T4;
+    // three 4-vectors per element of block J; reused for the column sums
+    // (2 x 4 waves x 256 values, which fit in the same space)
+    __shared__ T4 s_stage[3 * kTile];
+    __shared__ int s_next;
+    int t = blockIdx.x;
+    for (;;) {
+        if (persistent) {
+            __syncthreads();  // also ends the previous tile's use of s_stage
+            if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+            __syncthreads();
+            t = s_next;
+        }
+        if (t >= ntiles) break;
+        const int4 tile = tiles[t];
+        const Mol &M = mols[tile.x];
+        if (!(skip && M.st->done)) sym_tile<MIXED>(M, tile.y, tile.z, s_stage);
+        if (!persistent) break;
+    }
+}
+
 __global__ void reset_counter_kernel(int *counter) {
     if (threadIdx.x == 0) *counter = 0;
 }
@@ -265,12 +422,21 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(
                                          : M.u;
     double *out = MODE == kFinishDot ? M.w : MODE == kFinishRes ? M.res_out : M.y;
     const double dt = M.d_top, db = M.d_bot;
+    const bool f32 = precision != GABI_FP64 && M.sym32;  // float partial sums
+    const float *pf = reinterpret_cast<const float *>(M.part);
     double s = 0.0;
     for (int i = e.y * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
         double st = 0.0, sb = 0.0;
-        for (int p = 0; p < splits; ++p) {
-            st += M.part[(size_t)(2 * p) * n + i];
-            sb += M.part[(size_t)(2 * p + 1) * n + i];
+        if (f32) {
+            for (int p = 0; p < splits; ++p) {
+                st += (double)pf[(size_t)(2 * p) * n + i];
+                sb += (double)pf[(size_t)(2 * p + 1) * n + i];
+            }
+        } else {
+            for (int p = 0; p < splits; ++p) {
+                st += M.part[(size_t)(2 * p) * n + i];
+                sb += M.part[(size_t)(2 * p + 1) * n + i];
+            }
         }
         double yt = dt * v[i] - st;
         double yb = db * v[n + i] - sb;
@@ -318,6 +484,7 @@ void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, 
     }
 }
 
+// R = 2 or 1: split scheme with R rows per thread; R = 0: symmetric scheme
 template <bool MIXED, int R>
 static void pair_group(Batch &b, hipStream_t s, const int4 *tiles, int ntiles, int *counter,
                        int grid_cap, bool skip) {
@@ -327,15 +494,19 @@ static void pair_group(Batch &b, hipStream_t s, const int4 *tiles, int ntiles, i
         hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
         grid = std::min(ntiles, grid_cap);
     }
-    hipLaunchKernelGGL((pair_kernel<MIXED, R>), dim3(grid), dim3(kBlock), 0, s, b.d_mols, tiles,
-                       ntiles, counter, (int)b.persistent, (int)skip);
+    if constexpr (R == 0)
+        hipLaunchKernelGGL((sym_pair_kernel<MIXED>), dim3(grid), dim3(kBlock), 0, s, b.d_mols,
+                           tiles, ntiles, counter, (int)b.persistent, (int)skip);
+    else
+        hipLaunchKernelGGL((pair_kernel<MIXED, R>), dim3(grid), dim3(kBlock), 0, s, b.d_mols,
+                           tiles, ntiles, counter, (int)b.persistent, (int)skip);
 }
 
 void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer *t) {
     const bool mixed = precision != GABI_FP64;
     const int *cnt = mixed ? b.n_tiles32 : b.n_tiles64;
     const int4 *tiles = mixed ? b.d_tiles32 : b.d_tiles64;
-    if (cnt[0] + cnt[1] == 0) return;
+    if (cnt[0] + cnt[1] + cnt[2] == 0) return;
     const int pi = mixed ? 1 : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (t && t->pending[pi]) {
@@ -345,13 +516,16 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
             (void)hipEventRecord(e0, s);
         }
     }
-    int *c = b.d_counter + (mixed ? 2 : 0);
+    int *c = b.d_counter + (mixed ? 4 : 0);
+    const int4 *t1 = tiles + cnt[0], *t2 = t1 + cnt[1];
     if (mixed) {
         pair_group<true, 2>(b, s, tiles, cnt[0], c, b.grid32[0], skip);
-        pair_group<true, 1>(b, s, tiles + cnt[0], cnt[1], c + 1, b.grid32[1], skip);
+        pair_group<true, 1>(b, s, t1, cnt[1], c + 1, b.grid32[1], skip);
+        pair_group<true, 0>(b, s, t2, cnt[2], c + 2, b.grid32[2], skip);
     } else {
         pair_group<false, 2>(b, s, tiles, cnt[0], c, b.grid64[0], skip);
-        pair_group<false, 1>(b, s, tiles + cnt[0], cnt[1], c + 1, b.grid64[1], skip);
+        pair_group<false, 1>(b, s, t1, cnt[1], c + 1, b.grid64[1], skip);
+        pair_group<false, 0>(b, s, t2, cnt[2], c + 2, b.grid64[2], skip);
     }
     if (e0 && e1) {
         (void)hipEventRecord(e1, s);
@@ -372,25 +546,29 @@ void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j
                            precision, j, (int)skip);
 }
 
-template <bool MIXED, int R>
-static int resident_blocks() {
+template <typename K>
+static int resident_blocks(K kernel) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 1024;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_kernel<MIXED, R>, kBlock, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu * cus;
 }
 
-// Workgroups of the pair kernel (precision, R = 2 - rows_index) resident on
-// the whole device at once: the persistent grid size.
-int pair_occupancy_grid(int precision, int rows_index) {
+// Workgroups of a pair-kernel variant resident on the whole device at once
+// (the persistent grid size): variant 0 split with R = 2, 1 split with R = 1,
+// 2 symmetric.
+int pair_occupancy_grid(int precision, int variant) {
     if (precision == GABI_FP64)
-        return rows_index == 0 ? resident_blocks<false, 2>() : resident_blocks<false, 1>();
-    return rows_index == 0 ? resident_blocks<true, 2>() : resident_blocks<true, 1>();
+        return variant == 0   ? resident_blocks(pair_kernel<false, 2>)
+               : variant == 1 ? resident_blocks(pair_kernel<false, 1>)
+                              : resident_blocks(sym_pair_kernel<false>);
+    return variant == 0   ? resident_blocks(pair_kernel<true, 2>)
+           : variant == 1 ? resident_blocks(pair_kernel<true, 1>)
+                          : resident_blocks(sym_pair_kernel<true>);
 }
 
 }  // namespace gabi

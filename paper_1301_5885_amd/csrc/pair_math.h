@@ -136,4 +136,83 @@ __device__ __forceinline__ void pair_f32(
     bot = __builtin_fmaf(__builtin_fmaf(ux, k3, k4), rinv3, bot);
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric evaluation: one unordered pair of elements a (target i) and b
+// (target j) gives both the (target i, source j) and the (target j, source i)
+// terms.  With d = x_i - x_j the second uses the separation -d, the normal of
+// j and the weights of i:
+//   top_j += rinv [ (1-E) s_i - (eps A - 1) (d . m_i) rinv^2 ]
+//   bot_j += rinv^3 [ -(d . nu_j) ((A/eps - 1) s_i + (B-3) (d . m_i) rinv^2)
+//                     + (A-1) (nu_j . m_i) ]
+// rho, 1/rho, E, A and B are shared.  The (i, j) term is accumulated into
+// top/bot exactly as pair_f64/pair_f32 do, the (j, i) term into ctop/cbot.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SymElem {  // one element as a target and as a source
+    T x, y, z, nx, ny, nz, s, mx, my, mz;
+};
+
+__device__ __forceinline__ void sym_f64(const PairConstF64 &c, const SymElem<double> &a,
+                                        const SymElem<double> &b, double &top, double &bot,
+                                        double &ctop, double &cbot) {
+    const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+    const double rinv = rsqrt_f64(r2);
+    const double rinv2 = rinv * rinv;
+    const double rinv3 = rinv2 * rinv;
+    const double tau = c.kappa * (r2 * rinv);
+    const double E = exp_neg_f64(tau);
+    const double A = __builtin_fma(E, tau, E);
+    const double B3 = __builtin_fma(E, __builtin_fma(tau, tau + 3.0, 3.0), -3.0);
+    const double a1 = __builtin_fma(A, c.inv_eps, -1.0);
+    const double a2 = __builtin_fma(c.eps, A, -1.0);
+    const double B3r2 = B3 * rinv2;
+    // target i, source j
+    const double ux = __builtin_fma(dx, a.nx, __builtin_fma(dy, a.ny, dz * a.nz));
+    const double w = __builtin_fma(dx, b.mx, __builtin_fma(dy, b.my, dz * b.mz));
+    const double qn = __builtin_fma(a.nx, b.mx, __builtin_fma(a.ny, b.my, a.nz * b.mz));
+    top = __builtin_fma(__builtin_fma(a2 * w, rinv2, __builtin_fma(-E, b.s, b.s)), rinv, top);
+    const double k3 = __builtin_fma(a1, b.s, -B3r2 * w);
+    bot = __builtin_fma(__builtin_fma(ux, k3, __builtin_fma(A, qn, -qn)), rinv3, bot);
+    // target j, source i
+    const double un = __builtin_fma(dx, b.nx, __builtin_fma(dy, b.ny, dz * b.nz));
+    const double wm = __builtin_fma(dx, a.mx, __builtin_fma(dy, a.my, dz * a.mz));
+    const double qj = __builtin_fma(b.nx, a.mx, __builtin_fma(b.ny, a.my, b.nz * a.mz));
+    ctop = __builtin_fma(__builtin_fma(-(a2 * wm), rinv2, __builtin_fma(-E, a.s, a.s)), rinv,
+                         ctop);
+    const double k3j = __builtin_fma(a1, a.s, B3r2 * wm);
+    cbot = __builtin_fma(__builtin_fma(-un, k3j, __builtin_fma(A, qj, -qj)), rinv3, cbot);
+}
+
+__device__ __forceinline__ void sym_f32(const PairConstF32 &c, const SymElem<float> &a,
+                                        const SymElem<float> &b, float &top, float &bot,
+                                        float &ctop, float &cbot) {
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rinv2 = rinv * rinv;
+    const float rinv3 = rinv2 * rinv;
+    const float rho = r2 * rinv;
+    const float tau = c.kappa * rho;
+    const float E = __builtin_amdgcn_exp2f(rho * c.neg_kappa_log2e);
+    const float A = __builtin_fmaf(E, tau, E);
+    const float B3 = __builtin_fmaf(E, __builtin_fmaf(tau, tau + 3.0f, 3.0f), -3.0f);
+    const float a1 = __builtin_fmaf(A, c.inv_eps, -1.0f);
+    const float a2 = __builtin_fmaf(c.eps, A, -1.0f);
+    const float B3r2 = B3 * rinv2;
+    const float ux = __builtin_fmaf(dx, a.nx, __builtin_fmaf(dy, a.ny, dz * a.nz));
+    const float w = __builtin_fmaf(dx, b.mx, __builtin_fmaf(dy, b.my, dz * b.mz));
+    const float qn = __builtin_fmaf(a.nx, b.mx, __builtin_fmaf(a.ny, b.my, a.nz * b.mz));
+    top = __builtin_fmaf(__builtin_fmaf(a2 * w, rinv2, __builtin_fmaf(-E, b.s, b.s)), rinv, top);
+    const float k3 = __builtin_fmaf(a1, b.s, -B3r2 * w);
+    bot = __builtin_fmaf(__builtin_fmaf(ux, k3, __builtin_fmaf(A, qn, -qn)), rinv3, bot);
+    const float un = __builtin_fmaf(dx, b.nx, __builtin_fmaf(dy, b.ny, dz * b.nz));
+    const float wm = __builtin_fmaf(dx, a.mx, __builtin_fmaf(dy, a.my, dz * a.mz));
+    const float qj = __builtin_fmaf(b.nx, a.mx, __builtin_fmaf(b.ny, a.my, b.nz * a.mz));
+    ctop = __builtin_fmaf(__builtin_fmaf(-(a2 * wm), rinv2, __builtin_fmaf(-E, a.s, a.s)), rinv,
+                          ctop);
+    const float k3j = __builtin_fmaf(a1, a.s, B3r2 * wm);
+    cbot = __builtin_fmaf(__builtin_fmaf(-un, k3j, __builtin_fmaf(A, qj, -qj)), rinv3, cbot);
+}
+
 }  // namespace gabi

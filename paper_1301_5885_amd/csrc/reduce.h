@@ -22,3 +22,22 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 }
 
 }  // namespace gabi
+
+namespace gabi {
+
+// Rotation of a value across the 64 lanes of a wave by one lane (DPP
+// wave_ror:1): after 64 rotations every value is back in its lane.  All 64
+// lanes must be active.
+__device__ __forceinline__ float wave_rotate(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double wave_rotate(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, 0x13C, 0xf, 0xf, true);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0x13C, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+}  // namespace gabi

@@ -28,6 +28,7 @@ void init_table_locked() {
     for (int p = 0; p < 2; ++p)
         for (int b = 0; b < kBuckets; ++b) {
             TuneEntry e;
+            e.scheme = GABI_SCHEME_SPLIT;
             e.rows_per_thread = b >= 13 ? 2 : 1;  // N >= 8192: two rows per thread
             e.target_blocks = 2048;
             g_table[p][b] = e;
@@ -44,7 +45,9 @@ TuneEntry tune_entry(int precision, int64_t n) {
 
 int set_tune_entry(int precision, int bucket, TuneEntry e) {
     if (bucket < 0 || bucket >= kBuckets) return GABI_EINVAL;
+    if (e.scheme != GABI_SCHEME_SPLIT && e.scheme != GABI_SCHEME_SYMMETRIC) return GABI_EINVAL;
     if (e.rows_per_thread != 1 && e.rows_per_thread != 2) return GABI_EINVAL;
+    if (e.scheme == GABI_SCHEME_SYMMETRIC && e.rows_per_thread != 1) return GABI_EINVAL;
     if (e.target_blocks < 1 || e.target_blocks > (1 << 20)) return GABI_EINVAL;
     if (e.tail_pieces < 0 || e.tail_pieces > 4096) return GABI_EINVAL;
     std::lock_guard<std::mutex> lk(g_table_mu);
@@ -62,6 +65,15 @@ void reset_tuning() {
 PairLaunch pair_launch(int64_t n, int precision) {
     const TuneEntry e = tune_entry(precision, n);
     PairLaunch L;
+    L.scheme = e.scheme;
+    if (e.scheme == GABI_SCHEME_SYMMETRIC) {
+        L.rows_per_thread = 1;
+        L.row_blocks = (int)((n + kTile - 1) / kTile);
+        L.tiles_per_split = 1;
+        L.splits = L.head = L.row_blocks;
+        L.tail_start = (int)n;
+        return L;
+    }
     L.rows_per_thread = e.rows_per_thread;
     const int64_t rows_per_block = (int64_t)kBlock * L.rows_per_thread;
     L.row_blocks = (int)((n + rows_per_block - 1) / rows_per_block);
@@ -83,21 +95,23 @@ PairLaunch pair_launch(int64_t n, int precision) {
 
 }  // namespace gabi
 
-extern "C" int gabi_tune_set(int precision, int bucket, int rows_per_thread,
+extern "C" int gabi_tune_set(int precision, int bucket, int scheme, int rows_per_thread,
                              int target_blocks, int tail_pieces) {
     if (precision != GABI_FP64 && precision != GABI_FP32_PAIR) return GABI_EINVAL;
     gabi::TuneEntry e;
+    e.scheme = scheme;
     e.rows_per_thread = rows_per_thread;
     e.target_blocks = target_blocks;
     e.tail_pieces = tail_pieces;
     return gabi::set_tune_entry(precision, bucket, e);
 }
 
-extern "C" int gabi_tune_get(int precision, int bucket, int *rows_per_thread,
+extern "C" int gabi_tune_get(int precision, int bucket, int *scheme, int *rows_per_thread,
                              int *target_blocks, int *tail_pieces) {
     if ((precision != GABI_FP64 && precision != GABI_FP32_PAIR) || bucket < 0 || bucket >= 40)
         return GABI_EINVAL;
     const gabi::TuneEntry e = gabi::tune_entry(precision, int64_t(1) << bucket);
+    if (scheme) *scheme = e.scheme;
     if (rows_per_thread) *rows_per_thread = e.rows_per_thread;
     if (target_blocks) *target_blocks = e.target_blocks;
     if (tail_pieces) *tail_pieces = e.tail_pieces;
@@ -152,7 +166,11 @@ int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
     t.chg = c.take<double4>(nc);
     t.wgt = c.take<double4>(n);
     t.wgt32 = c.take<float4>(n);
-    t.part = c.take<double>(len * std::max(L64.splits, L32.splits));
+    // partial sums: FP64 per (row, split); the symmetric FP32-pair product keeps
+    // its per-block sums as float
+    const int64_t part64 = len * L64.splits * 8;
+    const int64_t part32 = len * L32.splits * (L32.scheme == GABI_SCHEME_SYMMETRIC ? 4 : 8);
+    t.part = c.take<double>((std::max(part64, part32) + 7) / 8);
     t.u = c.take<double>(len);
     t.y = c.take<double>(len);
     t.b = c.take<double>(len);
@@ -189,6 +207,9 @@ int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
         t.tail64 = L64.tail_start;
         t.head32 = L32.head;
         t.tail32 = L32.tail_start;
+        t.sym64 = L64.scheme == GABI_SCHEME_SYMMETRIC;
+        t.sym32 = L32.scheme == GABI_SCHEME_SYMMETRIC;
+        t.nbk = (int32_t)((n + kTile - 1) / kTile);
         t.rx_kblocks = kb;
         t.rx_tps = tps;
         t.rx_splits = sp;
@@ -278,7 +299,7 @@ void batch_free(Batch &b) {
     b.cap_bytes = 0;
     b.d_mols = nullptr;
     b.n_elem = b.n_blas = b.n_rx = 0;
-    b.n_tiles64[0] = b.n_tiles64[1] = b.n_tiles32[0] = b.n_tiles32[1] = 0;
+    for (int g = 0; g < 3; ++g) b.n_tiles64[g] = b.n_tiles32[g] = 0;
 }
 
 int batch_build(Batch &b, hipStream_t stream, std::string &err) {
@@ -292,37 +313,47 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         const int eb = (M.n + kBlock - 1) / kBlock;
         for (int i = 0; i < eb; ++i) elem.push_back(make_int2(k, i));
         for (int i = 0; i < M.nb; ++i) blas.push_back(make_int2(k, i));
-        // (mol, row block, split, cost = rows per thread x sources)
-        for (int sp = 0; sp < M.sp64; ++sp) {
-            int j0, j1;
-            split_range(M.n, M.tps64, M.head64, M.tail64, sp, j0, j1);
-            for (int rb = 0; rb < M.rb64; ++rb) t64.push_back(make_int4(k, rb, sp, M.R64 * (j1 - j0)));
-        }
-        for (int sp = 0; sp < M.sp32; ++sp) {
-            int j0, j1;
-            split_range(M.n, M.tps32, M.head32, M.tail32, sp, j0, j1);
-            for (int rb = 0; rb < M.rb32; ++rb) t32.push_back(make_int4(k, rb, sp, M.R32 * (j1 - j0)));
-        }
+        // split scheme: (mol, row block, split, cost = rows per thread x
+        // sources); symmetric scheme: (mol, block I, block J >= I, cost), an
+        // off-diagonal pair costing two diagonal ones
+        auto tiles = [&](std::vector<int4> &t, int sym, int R, int rb, int sp, int tps, int head,
+                         int tail) {
+            if (sym) {
+                for (int I = 0; I < M.nbk; ++I)
+                    for (int J = I; J < M.nbk; ++J)
+                        t.push_back(make_int4(k, I, J, (I == J ? 1 : 2) * kTile));
+                return;
+            }
+            for (int s = 0; s < sp; ++s) {
+                int j0, j1;
+                split_range(M.n, tps, head, tail, s, j0, j1);
+                for (int r = 0; r < rb; ++r) t.push_back(make_int4(k, r, s, R * (j1 - j0)));
+            }
+        };
+        tiles(t64, M.sym64, M.R64, M.rb64, M.sp64, M.tps64, M.head64, M.tail64);
+        tiles(t32, M.sym32, M.R32, M.rb32, M.sp32, M.tps32, M.head32, M.tail32);
         if (M.nc > 0)
             for (int sp = 0; sp < M.rx_splits; ++sp)
                 for (int kb = 0; kb < M.rx_kblocks; ++kb) rx.push_back(make_int4(k, kb, sp, 0));
     }
-    // group by rows per thread (two first), longest tiles first within a
-    // group; ties keep molecule and tile order
+    // group by kernel variant (split with two rows per thread, split with one,
+    // symmetric), longest tiles first within a group; ties keep molecule and
+    // tile order
     auto group = [&](std::vector<int4> &t, bool mixed, int *counts) {
-        auto R = [&](const int4 &a) {
+        auto G = [&](const int4 &a) {
             const Mol &M = b.slots[a.x]->mol;
-            return mixed ? M.R32 : M.R64;
+            if (mixed ? M.sym32 : M.sym64) return 2;
+            return (mixed ? M.R32 : M.R64) == 2 ? 0 : 1;
         };
         std::stable_sort(t.begin(), t.end(), [&](const int4 &a, const int4 &c) {
-            const int ra = R(a), rc = R(c);
-            if (ra != rc) return ra > rc;
+            const int ga = G(a), gc = G(c);
+            if (ga != gc) return ga < gc;
             return a.w > c.w;
         });
-        counts[0] = counts[1] = 0;
-        for (const int4 &a : t) counts[R(a) == 2 ? 0 : 1]++;
+        counts[0] = counts[1] = counts[2] = 0;
+        for (const int4 &a : t) counts[G(a)]++;
     };
-    int c64[2], c32[2];
+    int c64[3], c32[3];
     group(t64, false, c64);
     group(t32, true, c32);
 
@@ -376,10 +407,10 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     b.d_status = reinterpret_cast<KrylovStatus *>(base + o_st);
     b.n_elem = (int)elem.size();
     b.n_blas = (int)blas.size();
-    b.n_tiles64[0] = c64[0];
-    b.n_tiles64[1] = c64[1];
-    b.n_tiles32[0] = c32[0];
-    b.n_tiles32[1] = c32[1];
+    for (int g = 0; g < 3; ++g) {
+        b.n_tiles64[g] = c64[g];
+        b.n_tiles32[g] = c32[g];
+    }
     b.n_rx = (int)rx.size();
     // stage everything in the pinned buffer, one upload
     char *h = reinterpret_cast<char *>(b.h_pinned);
@@ -397,17 +428,17 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         return GABI_EDEVICE;
     }
     b.h_status = reinterpret_cast<KrylovStatus *>(h + o_st);
-    static int grid[2][2] = {{0, 0}, {0, 0}};
+    static int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};
     static std::once_flag once;
     std::call_once(once, [] {
-        for (int r = 0; r < 2; ++r) {
-            grid[0][r] = pair_occupancy_grid(GABI_FP64, r);
-            grid[1][r] = pair_occupancy_grid(GABI_FP32_PAIR, r);
+        for (int v = 0; v < 3; ++v) {
+            grid[0][v] = pair_occupancy_grid(GABI_FP64, v);
+            grid[1][v] = pair_occupancy_grid(GABI_FP32_PAIR, v);
         }
     });
-    for (int r = 0; r < 2; ++r) {
-        b.grid64[r] = grid[0][r];
-        b.grid32[r] = grid[1][r];
+    for (int v = 0; v < 3; ++v) {
+        b.grid64[v] = grid[0][v];
+        b.grid32[v] = grid[1][v];
     }
     return GABI_OK;
 }

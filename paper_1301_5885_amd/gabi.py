@@ -24,6 +24,7 @@ OK, NOT_CONVERGED = 0, 1
 EINVAL, ESTATE, EMESH, ENOMEM, EDEVICE, EBUSY = -1, -2, -3, -4, -5, -6
 FP64, FP32_PAIR = 0, 1
 SOLVE_FP64, SOLVE_MIXED_IR = 0, 1
+SCHEME_SPLIT, SCHEME_SYMMETRIC = 0, 1
 _NAMES = {0: "GABI_OK", 1: "GABI_NOT_CONVERGED", -1: "GABI_EINVAL",
           -2: "GABI_ESTATE", -3: "GABI_EMESH", -4: "GABI_ENOMEM",
           -5: "GABI_EDEVICE", -6: "GABI_EBUSY"}
@@ -146,8 +147,8 @@ def load():
     lib.gabi_device_bytes.restype = C.c_int64
     lib.gabi_set_kernel_timing.argtypes = [ctx, C.c_int]
     lib.gabi_kernel_time.argtypes = [ctx, C.c_int, _dp, C.POINTER(C.c_int64), C.c_int]
-    lib.gabi_tune_set.argtypes = [C.c_int] * 5
-    lib.gabi_tune_get.argtypes = [C.c_int, C.c_int] + [C.POINTER(C.c_int)] * 3
+    lib.gabi_tune_set.argtypes = [C.c_int] * 6
+    lib.gabi_tune_get.argtypes = [C.c_int, C.c_int] + [C.POINTER(C.c_int)] * 4
     lib.gabi_solve_footprint.argtypes = [_i64, _i64, C.c_int32]
     lib.gabi_solve_footprint.restype = C.c_int64
     lib.gabi_batch_solve.argtypes = [C.c_int, _i64, C.POINTER(ProblemC),
@@ -184,26 +185,28 @@ def _apply_tuning(lib):
         table = json.load(f)
     for key, prec in (("fp64", FP64), ("fp32", FP32_PAIR)):
         for bucket, e in table.get("entries", {}).get(key, {}).items():
-            rc = lib.gabi_tune_set(prec, int(bucket), int(e["rows_per_thread"]),
-                                   int(e["target_blocks"]), int(e.get("tail_pieces", 0)))
+            rc = lib.gabi_tune_set(prec, int(bucket), int(e.get("scheme", SCHEME_SPLIT)),
+                                   int(e["rows_per_thread"]), int(e["target_blocks"]),
+                                   int(e.get("tail_pieces", 0)))
             if rc != OK:
                 raise GabiError(rc, f"bad tuning entry {key}/{bucket} in {path}")
 
 
-def tune_set(precision, bucket, rows_per_thread, target_blocks, tail_pieces=0):
-    rc = load().gabi_tune_set(int(precision), int(bucket), int(rows_per_thread),
+def tune_set(precision, bucket, scheme, rows_per_thread, target_blocks, tail_pieces=0):
+    rc = load().gabi_tune_set(int(precision), int(bucket), int(scheme), int(rows_per_thread),
                               int(target_blocks), int(tail_pieces))
     if rc != OK:
         raise GabiError(rc, "gabi_tune_set")
 
 
 def tune_get(precision, bucket):
-    """(rows_per_thread, target_blocks, tail_pieces) of a table entry."""
-    r, t, p = C.c_int(), C.c_int(), C.c_int()
-    rc = load().gabi_tune_get(int(precision), int(bucket), C.byref(r), C.byref(t), C.byref(p))
+    """(scheme, rows_per_thread, target_blocks, tail_pieces) of a table entry."""
+    sc, r, t, p = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    rc = load().gabi_tune_get(int(precision), int(bucket), C.byref(sc), C.byref(r), C.byref(t),
+                              C.byref(p))
     if rc != OK:
         raise GabiError(rc, "gabi_tune_get")
-    return r.value, t.value, p.value
+    return sc.value, r.value, t.value, p.value
 
 
 def _f64(a):

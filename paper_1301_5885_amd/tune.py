@@ -85,7 +85,8 @@ def tune(buckets, reps, out_path):
         raise RuntimeError("the autotuner needs a GPU")
     gabi.load()
     table = {"device": torch.cuda.get_device_name(0), "reps": reps,
-             "candidates": {"rows_per_thread": list(ROWS), "target_blocks": list(TARGET_BLOCKS),
+             "candidates": {"schemes": ["split", "symmetric"], "rows_per_thread": list(ROWS),
+                            "target_blocks": list(TARGET_BLOCKS),
                             "tail_pieces": [0] + list(TAILS)},
              "entries": {k: {} for k in PRECISIONS}, "sweep": {k: {} for k in PRECISIONS}}
     t_start = time.time()
@@ -103,29 +104,34 @@ def tune(buckets, reps, out_path):
                     if key_rt in seen:
                         continue
                     seen.add(key_rt)
-                    gabi.tune_set(prec, b, R, tb, 0)
+                    gabi.tune_set(prec, b, gabi.SCHEME_SPLIT, R, tb, 0)
                     ms = time_product(V, F, prec, reps)
-                    rows.append((ms, R, tb, 0))
+                    rows.append((ms, gabi.SCHEME_SPLIT, R, tb, 0))
             rows.sort()
             untailed = rows[0]
-            for _, R, tb, _ in rows[:3]:
+            for _, _, R, tb, _ in rows[:3]:
                 for tail in TAILS:
                     if tail * 64 >= n // 2:
                         continue
-                    gabi.tune_set(prec, b, R, tb, tail)
+                    gabi.tune_set(prec, b, gabi.SCHEME_SPLIT, R, tb, tail)
                     ms = time_product(V, F, prec, reps)
-                    rows.append((ms, R, tb, tail))
+                    rows.append((ms, gabi.SCHEME_SPLIT, R, tb, tail))
+            gabi.tune_set(prec, b, gabi.SCHEME_SYMMETRIC, 1, 1, 0)
+            sym = time_product(V, F, prec, reps)
+            rows.append((sym, gabi.SCHEME_SYMMETRIC, 1, 1, 0))
             gabi.tune_set(prec, b, *default)
             rows.sort()
-            ms, R, tb, tail = rows[0]
+            ms, sc, R, tb, tail = rows[0]
             pairs = n * (n - 1)
-            table["entries"][key][str(b)] = {"rows_per_thread": R, "target_blocks": tb,
-                                             "tail_pieces": tail, "n": n, "ms": round(ms, 5),
+            table["entries"][key][str(b)] = {"scheme": sc, "rows_per_thread": R,
+                                             "target_blocks": tb, "tail_pieces": tail, "n": n,
+                                             "ms": round(ms, 5),
                                              "gpairs_per_s": round(pairs / ms / 1e6, 2)}
-            table["sweep"][key][str(b)] = [[R, tb, t, round(m, 5)] for m, R, tb, t in rows]
-            log(f"bucket {b:2d} N={n:7d} {key}: best R={R} blocks={tb:6d} tail={tail:3d} "
-                f"{ms:9.4f} ms ({pairs / ms / 1e6:8.1f} Gpairs/s); best without tail "
-                f"{untailed[0]:.4f} ms; worst {rows[-1][0]:.4f} ms [{time.time() - t_start:.0f} s]")
+            table["sweep"][key][str(b)] = [[s_, R, tb, t, round(m, 5)] for m, s_, R, tb, t in rows]
+            log(f"bucket {b:2d} N={n:7d} {key}: best scheme={sc} R={R} blocks={tb:6d} "
+                f"tail={tail:3d} {ms:9.4f} ms ({pairs / ms / 1e6:8.1f} Gpairs/s); split without "
+                f"tail {untailed[0]:.4f} ms; symmetric {sym:.4f} ms; worst {rows[-1][0]:.4f} ms "
+                f"[{time.time() - t_start:.0f} s]")
     with open(out_path + ".tmp", "w") as f:
         json.dump(table, f, indent=1)
     os.replace(out_path + ".tmp", out_path)

@@ -89,15 +89,16 @@ def test_tuning_table_set_get_and_validation():
     out-of-range entries are rejected without changing the table."""
     before = gabi.tune_get(gabi.FP32_PAIR, 14)
     try:
-        gabi.tune_set(gabi.FP32_PAIR, 14, 2, 3000, 17)
-        assert gabi.tune_get(gabi.FP32_PAIR, 14) == (2, 3000, 17)
-        for bad in [(3, 100, 0), (1, 0, 0), (1, 1 << 21, 0), (1, 100, -1), (1, 100, 5000)]:
+        gabi.tune_set(gabi.FP32_PAIR, 14, gabi.SCHEME_SPLIT, 2, 3000, 17)
+        assert gabi.tune_get(gabi.FP32_PAIR, 14) == (gabi.SCHEME_SPLIT, 2, 3000, 17)
+        for bad in [(0, 3, 100, 0), (0, 1, 0, 0), (0, 1, 1 << 21, 0), (0, 1, 100, -1),
+                    (0, 1, 100, 5000), (2, 1, 100, 0), (gabi.SCHEME_SYMMETRIC, 2, 1, 0)]:
             with pytest.raises(gabi.GabiError) as e:
                 gabi.tune_set(gabi.FP32_PAIR, 14, *bad)
             assert e.value.code == gabi.EINVAL
         with pytest.raises(gabi.GabiError):
-            gabi.tune_set(gabi.FP64, 40, 1, 100, 0)
-        assert gabi.tune_get(gabi.FP32_PAIR, 14) == (2, 3000, 17)
+            gabi.tune_set(gabi.FP64, 40, gabi.SCHEME_SPLIT, 1, 100, 0)
+        assert gabi.tune_get(gabi.FP32_PAIR, 14) == (gabi.SCHEME_SPLIT, 2, 3000, 17)
     finally:
         gabi.tune_set(gabi.FP32_PAIR, 14, *before)
 
@@ -108,14 +109,20 @@ def test_footprint_follows_the_decomposition():
     saved = [gabi.tune_get(p, b) for p in (gabi.FP64, gabi.FP32_PAIR)]
     try:
         for p in (gabi.FP64, gabi.FP32_PAIR):
-            gabi.tune_set(p, b, 1, 64, 0)
+            gabi.tune_set(p, b, gabi.SCHEME_SPLIT, 1, 64, 0)
         small = gabi.solve_footprint(20480, 200, 10)
         for p in (gabi.FP64, gabi.FP32_PAIR):
-            gabi.tune_set(p, b, 1, 8192, 64)
+            gabi.tune_set(p, b, gabi.SCHEME_SPLIT, 1, 8192, 64)
         large = gabi.solve_footprint(20480, 200, 10)
         # 80 row blocks: one split of all 80 tiles, against 64 one-tile splits
         # of the first 16384 sources and 64 tail splits of the last 4096
         assert large - small == (128 - 1) * 2 * 20480 * 8
+        # symmetric: one partial per 256-source block (80), FP64 for both
+        # precisions' buffer since the FP64 sums are the larger
+        for p in (gabi.FP64, gabi.FP32_PAIR):
+            gabi.tune_set(p, b, gabi.SCHEME_SYMMETRIC, 1, 1, 0)
+        sym = gabi.solve_footprint(20480, 200, 10)
+        assert sym - small == (80 - 1) * 2 * 20480 * 8
     finally:
         for p, e in zip((gabi.FP64, gabi.FP32_PAIR), saved):
             gabi.tune_set(p, b, *e)

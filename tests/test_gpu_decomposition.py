@@ -1,8 +1,9 @@
 """GPU: products and solves under decompositions other than the tuned table.
 
-The decomposition (rows per thread, source splits, 64-source tail splits)
-changes only the order in which a row's terms are added, so every
-decomposition must meet the same bars against the oracle: FP64 product
+The decomposition (rows per thread, source splits, 64-source tail splits,
+or the symmetric scheme that evaluates each unordered pair once) changes only
+the order in which a row's terms are added and which shared quantities feed
+them, so every decomposition must meet the same bars against the oracle: FP64 product
 <= 1e-10, FP32-pair product within fp32_tol, and batched results bitwise
 equal to the same request alone under that decomposition.  Each test sets the
 whole table before creating its contexts and restores it afterwards.
@@ -18,22 +19,22 @@ from test_gpu_parity import (CASES, EPS1, EPS2, KAPPA, fp32_tol, load, log, rel,
 
 pytestmark = pytest.mark.gpu
 
-# (rows per thread, target workgroups, tail pieces)
+# (scheme, rows per thread, target workgroups, tail pieces)
 LAYOUTS = {
-    "one_row_tail16": (1, 8192, 16),
-    "two_rows_tail5": (2, 2048, 5),
-    "coarse_no_tail": (2, 64, 0),
-    "all_tail": (1, 1, 4096),     # every split is a 64-source piece
+    "one_row_tail16": (gabi.SCHEME_SPLIT, 1, 8192, 16),
+    "two_rows_tail5": (gabi.SCHEME_SPLIT, 2, 2048, 5),
+    "coarse_no_tail": (gabi.SCHEME_SPLIT, 2, 64, 0),
+    "all_tail": (gabi.SCHEME_SPLIT, 1, 1, 4096),   # every split is a 64-source piece
+    "symmetric": (gabi.SCHEME_SYMMETRIC, 1, 1, 0),
 }
 
 
 @pytest.fixture
 def layout(request):
     saved = {(p, b): gabi.tune_get(p, b) for p in (gabi.FP64, gabi.FP32_PAIR) for b in range(40)}
-    R, tb, tail = LAYOUTS[request.param]
     for p in (gabi.FP64, gabi.FP32_PAIR):
         for b in range(40):
-            gabi.tune_set(p, b, R, tb, tail)
+            gabi.tune_set(p, b, *LAYOUTS[request.param])
     yield request.param
     for (p, b), e in saved.items():
         gabi.tune_set(p, b, *e)
@@ -57,7 +58,7 @@ def test_products_under_layout(layout, name):
         assert np.array_equal(ctx.matvec(u, gabi.FP32_PAIR), y32)
 
 
-@pytest.mark.parametrize("layout", ["one_row_tail16", "all_tail"], indirect=True)
+@pytest.mark.parametrize("layout", ["one_row_tail16", "all_tail", "symmetric"], indirect=True)
 def test_batch_bitwise_alone_under_layout(layout):
     probs = [star_problem(9, 12.0, 40, 7), star_problem(15, 16.0, 110, 8),
              star_problem(11, 13.0, 60, 21)]
