@@ -407,16 +407,26 @@ __global__ void reset_counter_kernel(int *counter) {
 // MODE kFinishDot: w = D V_j - sum part, partials of <w, V_0>
 //      kFinishRes: res_out = res_b - (D res_x - sum part), partials of ||.||^2
 //      kFinishY:   y = D u - sum part
+// A workgroup of kFinishQ x 256 threads covers 256 elements per pass: thread
+// group q adds the partial slots [q S / kFinishQ, (q+1) S / kFinishQ) of its
+// element in slot order, and the groups' sums are added in group order, so
+// the result does not depend on the launch (bitwise reproducible) while four
+// times as many waves keep memory requests in flight.
+constexpr int kFinishQ = 4;
+
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void finish_kernel(
+__global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
     const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision,
     int j, int skip) {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double acc[2][kFinishQ - 1][kBlock];
+    __shared__ double lds[kBlock * kFinishQ / 64];
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
     if (skip && M.st->done) return;
     const int n = M.n, nb = M.nb;
+    const int q = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
     const int splits = precision == GABI_FP64 ? M.sp64 : M.sp32;
+    const int p0 = q * splits / kFinishQ, p1 = (q + 1) * splits / kFinishQ;
     const double *v = MODE == kFinishDot ? M.V + (size_t)j * 2 * n
                     : MODE == kFinishRes ? M.res_x
                                          : M.u;
@@ -425,31 +435,47 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(
     const bool f32 = precision != GABI_FP64 && M.sym32;  // float partial sums
     const float *pf = reinterpret_cast<const float *>(M.part);
     double s = 0.0;
-    for (int i = e.y * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+    for (int base = e.y * kBlock; base < n; base += nb * kBlock) {
+        const int i = base + t;
         double st = 0.0, sb = 0.0;
-        if (f32) {
-            for (int p = 0; p < splits; ++p) {
-                st += (double)pf[(size_t)(2 * p) * n + i];
-                sb += (double)pf[(size_t)(2 * p + 1) * n + i];
-            }
-        } else {
-            for (int p = 0; p < splits; ++p) {
-                st += M.part[(size_t)(2 * p) * n + i];
-                sb += M.part[(size_t)(2 * p + 1) * n + i];
+        if (i < n) {
+            if (f32) {
+                for (int p = p0; p < p1; ++p) {
+                    st += (double)pf[(size_t)(2 * p) * n + i];
+                    sb += (double)pf[(size_t)(2 * p + 1) * n + i];
+                }
+            } else {
+                for (int p = p0; p < p1; ++p) {
+                    st += M.part[(size_t)(2 * p) * n + i];
+                    sb += M.part[(size_t)(2 * p + 1) * n + i];
+                }
             }
         }
-        double yt = dt * v[i] - st;
-        double yb = db * v[n + i] - sb;
-        if constexpr (MODE == kFinishRes) {
-            yt = M.res_b[i] - yt;
-            yb = M.res_b[n + i] - yb;
+        if (q > 0) {
+            acc[0][q - 1][t] = st;
+            acc[1][q - 1][t] = sb;
         }
-        out[i] = yt;
-        out[n + i] = yb;
-        if constexpr (MODE == kFinishDot)
-            s = __builtin_fma(yt, M.V[i], __builtin_fma(yb, M.V[n + i], s));
-        else if constexpr (MODE == kFinishRes)
-            s = __builtin_fma(yt, yt, __builtin_fma(yb, yb, s));
+        __syncthreads();
+        if (q == 0 && i < n) {
+#pragma unroll
+            for (int r = 0; r < kFinishQ - 1; ++r) {
+                st += acc[0][r][t];
+                sb += acc[1][r][t];
+            }
+            double yt = dt * v[i] - st;
+            double yb = db * v[n + i] - sb;
+            if constexpr (MODE == kFinishRes) {
+                yt = M.res_b[i] - yt;
+                yb = M.res_b[n + i] - yb;
+            }
+            out[i] = yt;
+            out[n + i] = yb;
+            if constexpr (MODE == kFinishDot)
+                s = __builtin_fma(yt, M.V[i], __builtin_fma(yb, M.V[n + i], s));
+            else if constexpr (MODE == kFinishRes)
+                s = __builtin_fma(yt, yt, __builtin_fma(yb, yb, s));
+        }
+        __syncthreads();  // acc is reused by the next pass
     }
     if constexpr (MODE != kFinishY) {
         s = block_sum(s, lds);
@@ -534,7 +560,7 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
 }
 
 void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip) {
-    const dim3 g(b.n_blas), blk(kBlock);
+    const dim3 g(b.n_blas), blk(kBlock * kFinishQ);
     if (mode == kFinishDot)
         hipLaunchKernelGGL(finish_kernel<kFinishDot>, g, blk, 0, s, b.d_mols, b.d_blas,
                            precision, j, (int)skip);
