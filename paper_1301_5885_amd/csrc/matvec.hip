@@ -399,10 +399,6 @@ __global__ __launch_bounds__(kBlock) void sym_pair_kernel(
     }
 }
 
-__global__ void reset_counter_kernel(int *counter) {
-    if (threadIdx.x == 0) *counter = 0;
-}
-
 // ------------------------------------------------------------------ finish
 // MODE kFinishDot: w = D V_j - sum part, partials of <w, V_0>
 //      kFinishRes: res_out = res_b - (D res_x - sum part), partials of ||.||^2
@@ -413,13 +409,18 @@ __global__ void reset_counter_kernel(int *counter) {
 // the result does not depend on the launch (bitwise reproducible) while four
 // times as many waves keep memory requests in flight.
 constexpr int kFinishQ = 4;
+constexpr int kPairVariants = 3;  // split R = 2, split R = 1, symmetric
 
+// The finish also rearms the tile queues of the product it completes: the
+// pair launches of this precision start from a zero counter, and only the
+// finish that follows them reads or writes those counters in between.
 template <int MODE>
 __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
     const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision,
-    int j, int skip) {
+    int j, int skip, int *__restrict__ counters) {
     __shared__ double acc[2][kFinishQ - 1][kBlock];
     __shared__ double lds[kBlock * kFinishQ / 64];
+    if (blockIdx.x == 0 && threadIdx.x < kPairVariants) counters[threadIdx.x] = 0;
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
     if (skip && M.st->done) return;
@@ -515,11 +516,8 @@ template <bool MIXED, int R>
 static void pair_group(Batch &b, hipStream_t s, const int4 *tiles, int ntiles, int *counter,
                        int grid_cap, bool skip) {
     if (ntiles == 0) return;
-    int grid = ntiles;
-    if (b.persistent) {
-        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
-        grid = std::min(ntiles, grid_cap);
-    }
+    // the counter is zero: set by the batch upload, rearmed by every finish
+    const int grid = b.persistent ? std::min(ntiles, grid_cap) : ntiles;
     if constexpr (R == 0)
         hipLaunchKernelGGL((sym_pair_kernel<MIXED>), dim3(grid), dim3(kBlock), 0, s, b.d_mols,
                            tiles, ntiles, counter, (int)b.persistent, (int)skip);
@@ -561,15 +559,16 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
 
 void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip) {
     const dim3 g(b.n_blas), blk(kBlock * kFinishQ);
+    int *c = b.d_counter + (precision == GABI_FP64 ? 0 : 4);
     if (mode == kFinishDot)
         hipLaunchKernelGGL(finish_kernel<kFinishDot>, g, blk, 0, s, b.d_mols, b.d_blas,
-                           precision, j, (int)skip);
+                           precision, j, (int)skip, c);
     else if (mode == kFinishRes)
         hipLaunchKernelGGL(finish_kernel<kFinishRes>, g, blk, 0, s, b.d_mols, b.d_blas,
-                           precision, j, (int)skip);
+                           precision, j, (int)skip, c);
     else
         hipLaunchKernelGGL(finish_kernel<kFinishY>, g, blk, 0, s, b.d_mols, b.d_blas,
-                           precision, j, (int)skip);
+                           precision, j, (int)skip, c);
 }
 
 template <typename K>
