@@ -216,9 +216,13 @@ int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
  *                        (j, i) terms (K1 is symmetric; K2..K4 differ only
  *                        in which normal and weights they use).  Diagonal
  *                        blocks (I, I) evaluate their ordered pairs.  Row
- *                        partial sums are kept per 256-source block.
- *                        rows_per_thread must be 1; target_blocks and
- *                        tail_pieces are not used.
+ *                        partial sums are kept per 256-source block.  Block
+ *                        pairs in the band 1 <= J - I <= tail_pieces are
+ *                        taken as two half tiles (128 sources of J each; the
+ *                        second half's row sums get slots of their own), so
+ *                        short work items fill the device's last round.
+ *                        rows_per_thread must be 1; target_blocks is not
+ *                        used.
  *
  * Work items are taken longest first.  A row's partial sums are added in
  * source order, and the decomposition depends only on N, the precision and

@@ -27,8 +27,10 @@ constexpr double kCoulomb = 332.0716;  // kcal A / (mol e^2)
 // ---------------------------------------------------------------------------
 // Decomposition of one product: row blocks x source splits.  A function of
 // N and the precision (and the loaded tuning table) only.
-// Sources [0, tail_start) form `head` splits of tiles_per_split tiles of 256;
-// [tail_start, N) forms splits of kPiece sources.
+// Split scheme: sources [0, tail_start) form `head` splits of tiles_per_split
+// tiles of 256; [tail_start, N) forms splits of kPiece sources.  Symmetric
+// scheme: row_blocks = blocks of 256, head = the band K (block pairs with
+// 1 <= J - I <= K are taken as two half tiles), splits = row_blocks + K.
 struct PairLaunch {
     int scheme = GABI_SCHEME_SPLIT;  // symmetric: row_blocks = splits = blocks of 256
     int rows_per_thread = 1;
@@ -93,8 +95,9 @@ struct Mol {
     int32_t R64, rb64, tps64, sp64;   // FP64 product decomposition
     int32_t R32, rb32, tps32, sp32;   // FP32-pair product decomposition
     int32_t head64, tail64, head32, tail32;  // split source ranges (split_range)
-    // symmetric scheme per precision (then R = 1, rb = sp = nbk blocks of 256,
-    // and the FP32-pair partial sums are stored as float)
+    // symmetric scheme per precision (then R = 1, rb = nbk blocks of 256,
+    // headXX = the band K of block pairs split into half tiles, sp = nbk + K
+    // partial slots, and the FP32-pair partial sums are stored as float)
     int32_t sym64, sym32, nbk, pad_sym;
     int32_t rx_kblocks, rx_tps, rx_splits, maxit;
     double kappa, eps, inv_eps, d_top, d_bot, rhs_scale;

@@ -285,7 +285,7 @@ __device__ __forceinline__ SymElem<typename PairView<MIXED>::T> sym_load(const M
 }
 
 template <bool MIXED>
-__device__ __forceinline__ void sym_tile(const Mol &M, int I, int J,
+__device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
                                          typename PairView<MIXED>::T4 *s_stage) {
     using T = typename PairView<MIXED>::T;
     using T4 = typename PairView<MIXED>::T4;
@@ -305,12 +305,14 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J,
     }
     __syncthreads();
     T *part = reinterpret_cast<T *>(M.part);  // float for the FP32-pair product
+    // chunks of block J this tile covers: all four, or two for a half tile
+    const int c0 = half == 2 ? 2 : 0, c1 = half == 1 ? 2 : kTile / 64;
     T top = T(0), bot = T(0);
     T colt[kTile / 64], colb[kTile / 64];
 #pragma unroll
     for (int c = 0; c < kTile / 64; ++c) {
         colt[c] = colb[c] = T(0);
-        if (c * 64 >= cnt) continue;
+        if (c < c0 || c >= c1 || c * 64 >= cnt) continue;
         const T4 *ca = sa + c * 64, *cb = sb + c * 64, *cc = sc + c * 64;
         if (I == J) {
             for (int s = 0; s < 64; ++s) {
@@ -357,7 +359,7 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J,
             s_col[(2 * wave + 1) * kTile + c * 64 + lane] = colb[c];
         }
         __syncthreads();
-        if (tid < cnt) {
+        if (tid < cnt && tid >= c0 * 64 && tid < c1 * 64) {
             T ct = s_col[tid], cbs = s_col[kTile + tid];
 #pragma unroll
             for (int w = 1; w < kBlock / 64; ++w) {
@@ -369,8 +371,19 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J,
         }
     }
     if (act) {
-        part[(size_t)(2 * J) * n + i] = top;
-        part[(size_t)(2 * J + 1) * n + i] = bot;
+        // the second half of a band pair has its own slot past the block slots
+        const int nbk = M.nbk;
+        const int slot = half == 2 ? nbk + (J - I - 1) : J;
+        part[(size_t)(2 * slot) * n + i] = top;
+        part[(size_t)(2 * slot + 1) * n + i] = bot;
+        if (I == J) {
+            // band slots of this block without a partner block stay zero
+            const int band = (MIXED ? M.sp32 : M.sp64) - nbk;
+            for (int d = nbk - 1 - I; d < band; ++d) {
+                part[(size_t)(2 * (nbk + d)) * n + i] = T(0);
+                part[(size_t)(2 * (nbk + d) + 1) * n + i] = T(0);
+            }
+        }
     }
 }
 
@@ -394,7 +407,8 @@ __global__ __launch_bounds__(kBlock) void sym_pair_kernel(
         if (t >= ntiles) break;
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
-        if (!(skip && M.st->done)) sym_tile<MIXED>(M, tile.y, tile.z, s_stage);
+        if (!(skip && M.st->done))
+            sym_tile<MIXED>(M, tile.y, tile.z & 0xffffff, tile.z >> 24, s_stage);
         if (!persistent) break;
     }
 }

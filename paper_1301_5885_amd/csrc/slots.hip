@@ -70,7 +70,8 @@ PairLaunch pair_launch(int64_t n, int precision) {
         L.rows_per_thread = 1;
         L.row_blocks = (int)((n + kTile - 1) / kTile);
         L.tiles_per_split = 1;
-        L.splits = L.head = L.row_blocks;
+        L.head = std::min(e.tail_pieces, std::max(0, L.row_blocks - 1));  // the band
+        L.splits = L.row_blocks + L.head;
         L.tail_start = (int)n;
         return L;
     }
@@ -314,14 +315,23 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         for (int i = 0; i < eb; ++i) elem.push_back(make_int2(k, i));
         for (int i = 0; i < M.nb; ++i) blas.push_back(make_int2(k, i));
         // split scheme: (mol, row block, split, cost = rows per thread x
-        // sources); symmetric scheme: (mol, block I, block J >= I, cost), an
-        // off-diagonal pair costing two diagonal ones
+        // sources); symmetric scheme: (mol, block I, J | half << 24, cost) for
+        // J >= I, half = 0 a whole pair (cost two diagonal tiles), 1 and 2 the
+        // two halves of a pair in the band 1 <= J - I <= K (cost one each)
         auto tiles = [&](std::vector<int4> &t, int sym, int R, int rb, int sp, int tps, int head,
                          int tail) {
             if (sym) {
                 for (int I = 0; I < M.nbk; ++I)
-                    for (int J = I; J < M.nbk; ++J)
-                        t.push_back(make_int4(k, I, J, (I == J ? 1 : 2) * kTile));
+                    for (int J = I; J < M.nbk; ++J) {
+                        if (J == I) {
+                            t.push_back(make_int4(k, I, J, kTile));
+                        } else if (J - I <= head) {
+                            t.push_back(make_int4(k, I, J | (1 << 24), kTile));
+                            t.push_back(make_int4(k, I, J | (2 << 24), kTile));
+                        } else {
+                            t.push_back(make_int4(k, I, J, 2 * kTile));
+                        }
+                    }
                 return;
             }
             for (int s = 0; s < sp; ++s) {

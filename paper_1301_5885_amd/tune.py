@@ -10,7 +10,8 @@ last round.  This module times the whole product (pair kernel plus the
 ordered split reduction) on geodesic spheres of one representative size per
 N bucket (bucket = floor(log2 N)), for both pair precisions: first every
 (R, target_blocks) without a tail, then the three fastest of those with
-each tail length, and writes the fastest entry per bucket as JSON.  The
+each tail length, and the symmetric scheme with each band of half tiles, and
+writes the fastest entry per bucket as JSON.  The
 library applies that table when it is loaded (`gabi.TUNING_PATH`).
 
 The decomposition fixes the order of the row sums, so a table change
@@ -36,6 +37,7 @@ ROWS = (1, 2)
 TARGET_BLOCKS = (256, 512, 1024, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576, 32768,
                  49152, 65536, 98304, 131072, 196608, 262144)
 TAILS = (4, 8, 16, 32, 64, 128)
+BANDS = (0, 4, 8, 16, 24, 32, 48, 64)   # symmetric scheme: block pairs taken as half tiles
 PRECISIONS = {"fp64": gabi.FP64, "fp32": gabi.FP32_PAIR}
 
 
@@ -87,7 +89,7 @@ def tune(buckets, reps, out_path):
     table = {"device": torch.cuda.get_device_name(0), "reps": reps,
              "candidates": {"schemes": ["split", "symmetric"], "rows_per_thread": list(ROWS),
                             "target_blocks": list(TARGET_BLOCKS),
-                            "tail_pieces": [0] + list(TAILS)},
+                            "tail_pieces": [0] + list(TAILS), "bands": list(BANDS)},
              "entries": {k: {} for k in PRECISIONS}, "sweep": {k: {} for k in PRECISIONS}}
     t_start = time.time()
     for b in buckets:
@@ -116,9 +118,14 @@ def tune(buckets, reps, out_path):
                     gabi.tune_set(prec, b, gabi.SCHEME_SPLIT, R, tb, tail)
                     ms = time_product(V, F, prec, reps)
                     rows.append((ms, gabi.SCHEME_SPLIT, R, tb, tail))
-            gabi.tune_set(prec, b, gabi.SCHEME_SYMMETRIC, 1, 1, 0)
-            sym = time_product(V, F, prec, reps)
-            rows.append((sym, gabi.SCHEME_SYMMETRIC, 1, 1, 0))
+            sym_rows = []
+            for band in BANDS:
+                if band and band >= -(-n // 256):
+                    continue
+                gabi.tune_set(prec, b, gabi.SCHEME_SYMMETRIC, 1, 1, band)
+                sym_rows.append((time_product(V, F, prec, reps), gabi.SCHEME_SYMMETRIC, 1, 1, band))
+            rows += sym_rows
+            sym = min(sym_rows)[0]
             gabi.tune_set(prec, b, *default)
             rows.sort()
             ms, sc, R, tb, tail = rows[0]
@@ -129,8 +136,8 @@ def tune(buckets, reps, out_path):
                                              "gpairs_per_s": round(pairs / ms / 1e6, 2)}
             table["sweep"][key][str(b)] = [[s_, R, tb, t, round(m, 5)] for m, s_, R, tb, t in rows]
             log(f"bucket {b:2d} N={n:7d} {key}: best scheme={sc} R={R} blocks={tb:6d} "
-                f"tail={tail:3d} {ms:9.4f} ms ({pairs / ms / 1e6:8.1f} Gpairs/s); split without "
-                f"tail {untailed[0]:.4f} ms; symmetric {sym:.4f} ms; worst {rows[-1][0]:.4f} ms "
+                f"tail/band={tail:3d} {ms:9.4f} ms ({pairs / ms / 1e6:8.1f} Gpairs/s); split without "
+                f"tail {untailed[0]:.4f} ms; best symmetric {sym:.4f} ms; worst {rows[-1][0]:.4f} ms "
                 f"[{time.time() - t_start:.0f} s]")
     with open(out_path + ".tmp", "w") as f:
         json.dump(table, f, indent=1)

@@ -123,6 +123,10 @@ def test_footprint_follows_the_decomposition():
             gabi.tune_set(p, b, gabi.SCHEME_SYMMETRIC, 1, 1, 0)
         sym = gabi.solve_footprint(20480, 200, 10)
         assert sym - small == (80 - 1) * 2 * 20480 * 8
+        # a band of 16 half-tiled block pairs adds 16 slots per row
+        for p in (gabi.FP64, gabi.FP32_PAIR):
+            gabi.tune_set(p, b, gabi.SCHEME_SYMMETRIC, 1, 1, 16)
+        assert gabi.solve_footprint(20480, 200, 10) - sym == 16 * 2 * 20480 * 8
     finally:
         for p, e in zip((gabi.FP64, gabi.FP32_PAIR), saved):
             gabi.tune_set(p, b, *e)

@@ -26,6 +26,7 @@ LAYOUTS = {
     "coarse_no_tail": (gabi.SCHEME_SPLIT, 2, 64, 0),
     "all_tail": (gabi.SCHEME_SPLIT, 1, 1, 4096),   # every split is a 64-source piece
     "symmetric": (gabi.SCHEME_SYMMETRIC, 1, 1, 0),
+    "symmetric_band3": (gabi.SCHEME_SYMMETRIC, 1, 1, 3),   # pairs with J - I <= 3 halved
 }
 
 
@@ -58,7 +59,8 @@ def test_products_under_layout(layout, name):
         assert np.array_equal(ctx.matvec(u, gabi.FP32_PAIR), y32)
 
 
-@pytest.mark.parametrize("layout", ["one_row_tail16", "all_tail", "symmetric"], indirect=True)
+@pytest.mark.parametrize("layout", ["one_row_tail16", "all_tail", "symmetric", "symmetric_band3"],
+                         indirect=True)
 def test_batch_bitwise_alone_under_layout(layout):
     probs = [star_problem(9, 12.0, 40, 7), star_problem(15, 16.0, 110, 8),
              star_problem(11, 13.0, 60, 21)]
