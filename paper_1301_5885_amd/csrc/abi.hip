@@ -635,12 +635,10 @@ static int energy_impl(gabi_ctx *ctx, const void *u, hipMemcpyKind kind, double 
     if (u) {
         GABI_HIP(ctx, hipMemcpyAsync(ctx->slot.mol.u, u, sizeof(double) * 2 * ctx->n, kind,
                                      ctx->stream));
-        launch_prep(ctx->batch, ctx->stream, GABI_FP64, kPrepU, 0, false);
-    } else {
-        if (!ctx->have_solution) return fail(ctx, GABI_ESTATE, "no solution to evaluate");
-        launch_prep(ctx->batch, ctx->stream, GABI_FP64, kPrepSol, 0, false);
+    } else if (!ctx->have_solution) {
+        return fail(ctx, GABI_ESTATE, "no solution to evaluate");
     }
-    launch_reaction(ctx->batch, ctx->stream);
+    launch_reaction(ctx->batch, ctx->stream, u == nullptr);
     if (phi_host && ctx->nc)
         GABI_HIP(ctx, hipMemcpyAsync(phi_host, ctx->slot.mol.phi, sizeof(double) * ctx->nc,
                                      hipMemcpyDeviceToHost, ctx->stream));

@@ -225,7 +225,7 @@ int hip_fail(gabi_ctx *ctx, hipError_t e, const char *what);
     } while (0)
 
 // ---- launchers ---------------------------------------------------------------
-enum PrepMode { kPrepCycle0 = 0, kPrepCycleJ = 1, kPrepResX = 2, kPrepU = 3, kPrepSol = 4 };
+enum PrepMode { kPrepCycle0 = 0, kPrepCycleJ = 1, kPrepResX = 2, kPrepU = 3 };
 enum FinishMode { kFinishDot = 0, kFinishRes = 1, kFinishY = 2 };
 
 struct Timer {  // optional event pairs around product launches
@@ -258,7 +258,8 @@ void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j
 int pair_occupancy_grid(int precision, int variant);
 // sources.hip
 void launch_rhs(const Batch &b, hipStream_t s);
-void launch_reaction(const Batch &b, hipStream_t s);
+// phi_reac at the charges and the energy of u (from_sol: of the solution)
+void launch_reaction(const Batch &b, hipStream_t s, bool from_sol);
 // krylov.hip
 void enqueue_init(Batch &b, hipStream_t s, bool x0_given, const Timer *t);
 void enqueue_round(Batch &b, hipStream_t s, const Timer *t);

@@ -280,8 +280,7 @@ void enqueue_gather(Batch &b, hipStream_t s) {
 
 void enqueue_finalize(Batch &b, hipStream_t s) {
     launch_copy(b, s, kCopyResXToSol);
-    launch_prep(b, s, GABI_FP64, kPrepSol, 0, false);
-    launch_reaction(b, s);
+    launch_reaction(b, s, true);
 }
 
 // One round, eager or as a replay of the captured graph of this batch.

@@ -31,7 +31,7 @@ namespace gabi {
 // ------------------------------------------------------------------ prep
 // MODE (compile time) selects the input vector: the cycle start r/||r||
 // (stored as V_0), the Arnoldi vector w/h_{j,j-1} (stored as V_j), the
-// residual iterate, the product input u, or the kept solution.
+// residual iterate, or the product input u.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void prep_kernel(
     const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision,
@@ -45,7 +45,6 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
     const double *src = MODE == kPrepCycle0 ? M.cyc_src
                       : MODE == kPrepCycleJ ? M.w
                       : MODE == kPrepResX   ? M.res_x
-                      : MODE == kPrepSol    ? M.sol
                                             : M.u;
     double phi = src[i], psi = src[n + i];
     if constexpr (MODE == kPrepCycle0 || MODE == kPrepCycleJ) {
@@ -61,11 +60,16 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
     const double c = p.w * (1.0 / (4.0 * kPi));
     const double s = c * psi;
     const double t = c * phi;
+    // The symmetric product reads (s, t) and forms the m terms from the
+    // normal; the split product reads (s, m).
+    const bool sym = precision == GABI_FP64 ? M.sym64 : M.sym32;
     if (precision == GABI_FP64)
-        M.wgt[i] = make_double4(s, t * nu.x, t * nu.y, t * nu.z);
+        M.wgt[i] = sym ? make_double4(s, t, 0.0, 0.0)
+                       : make_double4(s, t * nu.x, t * nu.y, t * nu.z);
     else
-        M.wgt32[i] = make_float4((float)s, (float)(t * nu.x), (float)(t * nu.y),
-                                 (float)(t * nu.z));
+        M.wgt32[i] = sym ? make_float4((float)s, (float)t, 0.0f, 0.0f)
+                         : make_float4((float)s, (float)(t * nu.x), (float)(t * nu.y),
+                                       (float)(t * nu.z));
 }
 
 // ------------------------------------------------------------------ pair
@@ -244,9 +248,9 @@ __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
 
 // ------------------------------------------------------------- symmetric
 // Tile (I, J) of the symmetric scheme, one element of block I per thread.
-// The workgroup stages block J in LDS (three 4-vectors per element:
-// (x, y, z, s), (nx, ny, nz, mx), (my, mz, -, -)), taken in four chunks of 64
-// elements.  At step s of a chunk lane l reads element (l - s) mod 64, so the
+// The workgroup stages block J in LDS (two 4-vectors per element:
+// (x, y, z, s) and (nx, ny, nz, t), where m = t nu), taken in four chunks of
+// 64 elements.  At step s of a chunk lane l reads element (l - s) mod 64, so the
 // 64 lanes of a wave read 64 different elements (no bank conflicts) and meet
 // every element of the chunk once in 64 steps:
 //  * I < J: each unordered pair is evaluated once; the (i, j) terms add to the
@@ -277,10 +281,8 @@ __device__ __forceinline__ SymElem<typename PairView<MIXED>::T> sym_load(const M
     a.nx = q.x;
     a.ny = q.y;
     a.nz = q.z;
-    a.s = active ? w.x : T(0);
-    a.mx = active ? w.y : T(0);
-    a.my = active ? w.z : T(0);
-    a.mz = active ? w.w : T(0);
+    a.s = active ? w.x : T(0);  // weights (s, t) of the symmetric layout
+    a.t = active ? w.y : T(0);
     return a;
 }
 
@@ -296,12 +298,11 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
     const SymElem<T> a = sym_load<MIXED>(M, i, act, 1e17f);
     const int jt = J * kTile;
     const int cnt = min(kTile, n - jt);
-    T4 *sa = s_stage, *sb = s_stage + kTile, *sc = s_stage + 2 * kTile;
+    T4 *sa = s_stage, *sb = s_stage + kTile;  // (x, y, z, s) and (nx, ny, nz, t)
     {
         const SymElem<T> e = sym_load<MIXED>(M, jt + tid, tid < cnt, -1e17f);
         sa[tid] = T4{e.x, e.y, e.z, e.s};
-        sb[tid] = T4{e.nx, e.ny, e.nz, e.mx};
-        sc[tid] = T4{e.my, e.mz, T(0), T(0)};
+        sb[tid] = T4{e.nx, e.ny, e.nz, e.t};
     }
     __syncthreads();
     T *part = reinterpret_cast<T *>(M.part);  // float for the FP32-pair product
@@ -313,28 +314,28 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
     for (int c = 0; c < kTile / 64; ++c) {
         colt[c] = colb[c] = T(0);
         if (c < c0 || c >= c1 || c * 64 >= cnt) continue;
-        const T4 *ca = sa + c * 64, *cb = sb + c * 64, *cc = sc + c * 64;
+        const T4 *ca = sa + c * 64, *cb = sb + c * 64;
         if (I == J) {
             for (int s = 0; s < 64; ++s) {
                 const int k = (lane - s) & 63;
                 if (c == wave && s == 0) continue;  // i paired with itself
-                const T4 p = ca[k], q = cb[k], r = cc[k];
+                const T4 p = ca[k], q = cb[k];
                 if constexpr (MIXED) {
                     const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
-                    pair_f32(kc, a.x, a.y, a.z, a.nx, a.ny, a.nz, p.x, p.y, p.z, p.w, q.w, r.x,
-                             r.y, top, bot);
+                    pair_f32(kc, a.x, a.y, a.z, a.nx, a.ny, a.nz, p.x, p.y, p.z, p.w, q.w * q.x,
+                             q.w * q.y, q.w * q.z, top, bot);
                 } else {
                     const PairConstF64 kc{M.kappa, M.eps, M.inv_eps};
-                    pair_f64(kc, a.x, a.y, a.z, a.nx, a.ny, a.nz, p.x, p.y, p.z, p.w, q.w, r.x,
-                             r.y, top, bot);
+                    pair_f64(kc, a.x, a.y, a.z, a.nx, a.ny, a.nz, p.x, p.y, p.z, p.w, q.w * q.x,
+                             q.w * q.y, q.w * q.z, top, bot);
                 }
             }
         } else {
             T ctop = T(0), cbot = T(0);
             for (int s = 0; s < 64; ++s) {
                 const int k = (lane - s) & 63;
-                const T4 p = ca[k], q = cb[k], r = cc[k];
-                const SymElem<T> b{p.x, p.y, p.z, q.x, q.y, q.z, p.w, q.w, r.x, r.y};
+                const T4 p = ca[k], q = cb[k];
+                const SymElem<T> b{p.x, p.y, p.z, q.x, q.y, q.z, p.w, q.w};
                 if constexpr (MIXED) {
                     const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
                     sym_f32(kc, a, b, top, bot, ctop, cbot);
@@ -350,7 +351,8 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
         }
     }
     if (I != J) {
-        // the staging area is free once every wave is past its last chunk
+        // the staging area is free once every wave is past its last chunk; it
+        // holds exactly the 2 x 4 waves x 256 column sums
         T *s_col = reinterpret_cast<T *>(s_stage);
         __syncthreads();
 #pragma unroll
@@ -392,9 +394,9 @@ __global__ __launch_bounds__(kBlock) void sym_pair_kernel(
     const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
     int *__restrict__ counter, int persistent, int skip) {
     using T4 = typename PairView<MIXED>::T4;
-    // three 4-vectors per element of block J; reused for the column sums
-    // (2 x 4 waves x 256 values, which fit in the same space)
-    __shared__ T4 s_stage[3 * kTile];
+    // two 4-vectors per element of block J; reused for the column sums
+    // (2 x 4 waves x 256 values, the same size)
+    __shared__ T4 s_stage[2 * kTile];
     __shared__ int s_next;
     int t = blockIdx.x;
     for (;;) {
@@ -512,10 +514,6 @@ void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, 
             break;
         case kPrepResX:
             hipLaunchKernelGGL(prep_kernel<kPrepResX>, g, blk, 0, s, b.d_mols, b.d_elem,
-                               precision, j, (int)skip);
-            break;
-        case kPrepSol:
-            hipLaunchKernelGGL(prep_kernel<kPrepSol>, g, blk, 0, s, b.d_mols, b.d_elem,
                                precision, j, (int)skip);
             break;
         default:

@@ -139,17 +139,20 @@ __device__ __forceinline__ void pair_f32(
 // ---------------------------------------------------------------------------
 // Symmetric evaluation: one unordered pair of elements a (target i) and b
 // (target j) gives both the (target i, source j) and the (target j, source i)
-// terms.  With d = x_i - x_j the second uses the separation -d, the normal of
-// j and the weights of i:
-//   top_j += rinv [ (1-E) s_i - (eps A - 1) (d . m_i) rinv^2 ]
-//   bot_j += rinv^3 [ -(d . nu_j) ((A/eps - 1) s_i + (B-3) (d . m_i) rinv^2)
-//                     + (A-1) (nu_j . m_i) ]
-// rho, 1/rho, E, A and B are shared.  The (i, j) term is accumulated into
-// top/bot exactly as pair_f64/pair_f32 do, the (j, i) term into ctop/cbot.
+// terms.  With m = t nu (t = W phi / (4 pi)) and d = x_i - x_j:
+//   d . m_j = t_j (d . nu_j),   nu_i . m_j = t_j n,   n = nu_i . nu_j,
+//   d . m_i = t_i (d . nu_i),   nu_j . m_i = t_i n,
+// so the (j, i) term, which uses the separation -d, the normal of j and the
+// weights of i,
+//   top_j += rinv [ (1-E) s_i - (eps A - 1) t_i u_x rinv^2 ]
+//   bot_j += rinv^3 [ -u_j ((A/eps - 1) s_i + (B-3) t_i u_x rinv^2)
+//                     + (A-1) t_i n ],        u_x = d . nu_i, u_j = d . nu_j,
+// shares with the (i, j) term rho, 1/rho, E, A, B and the three dot products.
+// The (i, j) term accumulates into top/bot, the (j, i) term into ctop/cbot.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SymElem {  // one element as a target and as a source
-    T x, y, z, nx, ny, nz, s, mx, my, mz;
+    T x, y, z, nx, ny, nz, s, t;
 };
 
 __device__ __forceinline__ void sym_f64(const PairConstF64 &c, const SymElem<double> &a,
@@ -167,21 +170,20 @@ __device__ __forceinline__ void sym_f64(const PairConstF64 &c, const SymElem<dou
     const double a1 = __builtin_fma(A, c.inv_eps, -1.0);
     const double a2 = __builtin_fma(c.eps, A, -1.0);
     const double B3r2 = B3 * rinv2;
-    // target i, source j
     const double ux = __builtin_fma(dx, a.nx, __builtin_fma(dy, a.ny, dz * a.nz));
-    const double w = __builtin_fma(dx, b.mx, __builtin_fma(dy, b.my, dz * b.mz));
-    const double qn = __builtin_fma(a.nx, b.mx, __builtin_fma(a.ny, b.my, a.nz * b.mz));
+    const double uj = __builtin_fma(dx, b.nx, __builtin_fma(dy, b.ny, dz * b.nz));
+    const double nn = __builtin_fma(a.nx, b.nx, __builtin_fma(a.ny, b.ny, a.nz * b.nz));
+    // target i, source j
+    const double w = b.t * uj, qn = b.t * nn;
     top = __builtin_fma(__builtin_fma(a2 * w, rinv2, __builtin_fma(-E, b.s, b.s)), rinv, top);
     const double k3 = __builtin_fma(a1, b.s, -B3r2 * w);
     bot = __builtin_fma(__builtin_fma(ux, k3, __builtin_fma(A, qn, -qn)), rinv3, bot);
     // target j, source i
-    const double un = __builtin_fma(dx, b.nx, __builtin_fma(dy, b.ny, dz * b.nz));
-    const double wm = __builtin_fma(dx, a.mx, __builtin_fma(dy, a.my, dz * a.mz));
-    const double qj = __builtin_fma(b.nx, a.mx, __builtin_fma(b.ny, a.my, b.nz * a.mz));
+    const double wm = a.t * ux, qj = a.t * nn;
     ctop = __builtin_fma(__builtin_fma(-(a2 * wm), rinv2, __builtin_fma(-E, a.s, a.s)), rinv,
                          ctop);
     const double k3j = __builtin_fma(a1, a.s, B3r2 * wm);
-    cbot = __builtin_fma(__builtin_fma(-un, k3j, __builtin_fma(A, qj, -qj)), rinv3, cbot);
+    cbot = __builtin_fma(__builtin_fma(-uj, k3j, __builtin_fma(A, qj, -qj)), rinv3, cbot);
 }
 
 __device__ __forceinline__ void sym_f32(const PairConstF32 &c, const SymElem<float> &a,
@@ -201,18 +203,17 @@ __device__ __forceinline__ void sym_f32(const PairConstF32 &c, const SymElem<flo
     const float a2 = __builtin_fmaf(c.eps, A, -1.0f);
     const float B3r2 = B3 * rinv2;
     const float ux = __builtin_fmaf(dx, a.nx, __builtin_fmaf(dy, a.ny, dz * a.nz));
-    const float w = __builtin_fmaf(dx, b.mx, __builtin_fmaf(dy, b.my, dz * b.mz));
-    const float qn = __builtin_fmaf(a.nx, b.mx, __builtin_fmaf(a.ny, b.my, a.nz * b.mz));
+    const float uj = __builtin_fmaf(dx, b.nx, __builtin_fmaf(dy, b.ny, dz * b.nz));
+    const float nn = __builtin_fmaf(a.nx, b.nx, __builtin_fmaf(a.ny, b.ny, a.nz * b.nz));
+    const float w = b.t * uj, qn = b.t * nn;
     top = __builtin_fmaf(__builtin_fmaf(a2 * w, rinv2, __builtin_fmaf(-E, b.s, b.s)), rinv, top);
     const float k3 = __builtin_fmaf(a1, b.s, -B3r2 * w);
     bot = __builtin_fmaf(__builtin_fmaf(ux, k3, __builtin_fmaf(A, qn, -qn)), rinv3, bot);
-    const float un = __builtin_fmaf(dx, b.nx, __builtin_fmaf(dy, b.ny, dz * b.nz));
-    const float wm = __builtin_fmaf(dx, a.mx, __builtin_fmaf(dy, a.my, dz * a.mz));
-    const float qj = __builtin_fmaf(b.nx, a.mx, __builtin_fmaf(b.ny, a.my, b.nz * a.mz));
+    const float wm = a.t * ux, qj = a.t * nn;
     ctop = __builtin_fmaf(__builtin_fmaf(-(a2 * wm), rinv2, __builtin_fmaf(-E, a.s, a.s)), rinv,
                           ctop);
     const float k3j = __builtin_fmaf(a1, a.s, B3r2 * wm);
-    cbot = __builtin_fmaf(__builtin_fmaf(-un, k3j, __builtin_fmaf(A, qj, -qj)), rinv3, cbot);
+    cbot = __builtin_fmaf(__builtin_fmaf(-uj, k3j, __builtin_fmaf(A, qj, -qj)), rinv3, cbot);
 }
 
 }  // namespace gabi

@@ -55,8 +55,12 @@ void launch_rhs(const Batch &b, hipStream_t s) {
 
 // Reaction potential: thread = charge (target), tile = (molecule, charge
 // block, split of the surface elements); partial sums [split][nc].
+// The source weights s_j = W_j psi_j/(4 pi), m_j = W_j phi_j nu_j/(4 pi) of the
+// evaluated vector (the solution or the product input u) are formed while the
+// sources are staged, independent of the layout the products use.
 __global__ __launch_bounds__(kBlock) void reaction_kernel(const Mol *__restrict__ mols,
-                                                          const int4 *__restrict__ list) {
+                                                          const int4 *__restrict__ list,
+                                                          int from_sol) {
     __shared__ double4 s_pos[kTile];
     __shared__ double4 s_w[kTile];
     const int4 e = list[blockIdx.x];
@@ -74,8 +78,13 @@ __global__ __launch_bounds__(kBlock) void reaction_kernel(const Mol *__restrict_
         const int cnt = min(kTile, n - jt);
         __syncthreads();
         if (tid < cnt) {
-            s_pos[tid] = M.pos[jt + tid];
-            s_w[tid] = M.wgt[jt + tid];
+            const double *u = from_sol ? M.sol : M.u;
+            const double4 p = M.pos[jt + tid];
+            const double4 nu = M.nrm[jt + tid];
+            const double c = p.w * (1.0 / (4.0 * kPi));
+            const double t = c * u[jt + tid];
+            s_pos[tid] = p;
+            s_w[tid] = make_double4(c * u[n + jt + tid], t * nu.x, t * nu.y, t * nu.z);
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; ++jj) {
@@ -112,9 +121,10 @@ __global__ __launch_bounds__(kBlock) void reaction_finish_kernel(const Mol *__re
     if (threadIdx.x == 0) M.st->energy = 0.5 * tot * 4.0 * kPi * kCoulomb;
 }
 
-void launch_reaction(const Batch &b, hipStream_t s) {
+void launch_reaction(const Batch &b, hipStream_t s, bool from_sol) {
     if (b.n_rx > 0)
-        hipLaunchKernelGGL(reaction_kernel, dim3(b.n_rx), dim3(kBlock), 0, s, b.d_mols, b.d_rx);
+        hipLaunchKernelGGL(reaction_kernel, dim3(b.n_rx), dim3(kBlock), 0, s, b.d_mols, b.d_rx,
+                           (int)from_sol);
     hipLaunchKernelGGL(reaction_finish_kernel, dim3((int)b.slots.size()), dim3(kBlock), 0, s,
                        b.d_mols);
 }
