@@ -298,11 +298,14 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
     const SymElem<T> a = sym_load<MIXED>(M, i, act, 1e17f);
     const int jt = J * kTile;
     const int cnt = min(kTile, n - jt);
-    T4 *sa = s_stage, *sb = s_stage + kTile;  // (x, y, z, s) and (nx, ny, nz, t)
+    // (x, y, z, s) and (nx, ny, nz, t); each chunk of 64 is stored twice in a
+    // row, so element (l - s) mod 64 is entry l + 64 - s of its chunk copy
+    T4 *sa = s_stage, *sb = s_stage + 2 * kTile;
     {
         const SymElem<T> e = sym_load<MIXED>(M, jt + tid, tid < cnt, -1e17f);
-        sa[tid] = T4{e.x, e.y, e.z, e.s};
-        sb[tid] = T4{e.nx, e.ny, e.nz, e.t};
+        const int at = (tid >> 6) * 128 + (tid & 63);
+        sa[at] = sa[at + 64] = T4{e.x, e.y, e.z, e.s};
+        sb[at] = sb[at + 64] = T4{e.nx, e.ny, e.nz, e.t};
     }
     __syncthreads();
     T *part = reinterpret_cast<T *>(M.part);  // float for the FP32-pair product
@@ -311,13 +314,14 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
     T top = T(0), bot = T(0);
     T colt[kTile / 64], colb[kTile / 64];
 #pragma unroll
-    for (int c = 0; c < kTile / 64; ++c) {
-        colt[c] = colb[c] = T(0);
-        if (c < c0 || c >= c1 || c * 64 >= cnt) continue;
-        const T4 *ca = sa + c * 64, *cb = sb + c * 64;
+    for (int c = 0; c < kTile / 64; ++c) colt[c] = colb[c] = T(0);
+#pragma unroll 1
+    for (int c = c0; c < c1; ++c) {
+        if (c * 64 >= cnt) break;
+        const T4 *ca = sa + c * 128 + lane + 64, *cb = sb + c * 128 + lane + 64;
         if (I == J) {
             for (int s = 0; s < 64; ++s) {
-                const int k = (lane - s) & 63;
+                const int k = -s;
                 if (c == wave && s == 0) continue;  // i paired with itself
                 const T4 p = ca[k], q = cb[k];
                 if constexpr (MIXED) {
@@ -332,9 +336,9 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
             }
         } else {
             T ctop = T(0), cbot = T(0);
+#pragma unroll 8
             for (int s = 0; s < 64; ++s) {
-                const int k = (lane - s) & 63;
-                const T4 p = ca[k], q = cb[k];
+                const T4 p = ca[-s], q = cb[-s];
                 const SymElem<T> b{p.x, p.y, p.z, q.x, q.y, q.z, p.w, q.w};
                 if constexpr (MIXED) {
                     const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
@@ -346,8 +350,13 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
                 ctop = wave_rotate(ctop);
                 cbot = wave_rotate(cbot);
             }
-            colt[c] = ctop;
-            colb[c] = cbot;
+            // (registers are indexed by the chunk, so select rather than index)
+#pragma unroll
+            for (int cc = 0; cc < kTile / 64; ++cc)
+                if (cc == c) {
+                    colt[cc] = ctop;
+                    colb[cc] = cbot;
+                }
         }
     }
     if (I != J) {
@@ -389,14 +398,15 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
     }
 }
 
+// The FP32-pair variant is held to 8 waves per SIMD (at most 64 VGPRs).
 template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void sym_pair_kernel(
+__global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
     const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
     int *__restrict__ counter, int persistent, int skip) {
     using T4 = typename PairView<MIXED>::T4;
-    // two 4-vectors per element of block J; reused for the column sums
-    // (2 x 4 waves x 256 values, the same size)
-    __shared__ T4 s_stage[2 * kTile];
+    // two 4-vectors per element of block J, each chunk stored twice; reused
+    // for the column sums (2 x 4 waves x 256 values)
+    __shared__ T4 s_stage[4 * kTile];
     __shared__ int s_next;
     int t = blockIdx.x;
     for (;;) {
