@@ -42,8 +42,8 @@ def layout(request):
 
 
 @pytest.mark.parametrize("layout", list(LAYOUTS), indirect=True)
-@pytest.mark.parametrize("name", ["born_1280", "star_1620_ragged", "star_4500_ragged",
-                                  "star_10580_ragged_r2"])
+@pytest.mark.parametrize("name", ["tetra_4", "ico_80", "born_1280", "star_1620_ragged",
+                                  "star_4500_ragged", "star_10580_ragged_r2"])
 def test_products_under_layout(layout, name):
     V, F, pos, q = CASES[name]()
     log(f"[layout {layout}] {name} N={len(F)}")

@@ -68,8 +68,18 @@ def load(ctx, V, F, pos, q, eps1=EPS1, eps2=EPS2, kappa=KAPPA):
     return oracle.mesh_elements(V, F)
 
 
+def tetrahedron():
+    """The smallest closed surface: 4 faces, counter-clockwise from outside."""
+    V = np.array([[1.0, 1.0, 1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0]])
+    F = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]], dtype=np.int32)
+    return V, F, np.array([[0.1, -0.2, 0.05]]), np.array([0.7])
+
+
 CASES = {
-    # name: (V, F, pos, q) builders; sizes span 1..80 tiles and ragged tails
+    # name: (V, F, pos, q) builders; sizes span part of one 64-element chunk
+    # to 80 tiles, with ragged tails
+    "tetra_4": tetrahedron,
+    "ico_80": lambda: (*icosphere(2, 1.5), np.zeros((1, 3)), np.ones(1)),
     "born_1280": lambda: (*icosphere(8, 2.0), np.zeros((1, 3)), np.ones(1)),
     "star_1620_ragged": lambda: star_problem(9, 12.0, 40, 7),
     "star_4500_ragged": lambda: star_problem(15, 16.0, 110, 8),
