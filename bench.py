@@ -85,6 +85,22 @@ def traffic_from_profiles(kernel_key, workload):
     return rec.get("bytes_per_launch")
 
 
+def valu_from_profiles(kernel_key, workload, avg_s):
+    """Hardware VALU FLOPs per launch from the committed counter summary (if
+    taken on the current kernel source), over this run's launch time."""
+    path = os.path.join(ROOT, "profiles", f"valu_flops_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel_key)
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    tf = rec["hw_flop_per_launch"] / avg_s / 1e12
+    return {"hw_flop_per_launch": rec["hw_flop_per_launch"], "tflops": round(tf, 3),
+            "frac": round(tf / rec["peak"], 4),
+            "source": f"rocprofv3 SQ_INSTS_VALU_FLOPS_* (profiles/valu_flops_{workload}.md)"}
+
+
 def golden_energy(workload):
     path = os.path.join(ROOT, "tests", "golden", f"{workload}_reference.json")
     if not os.path.exists(path):
@@ -147,6 +163,7 @@ def roofline(res, key, n, workload, gabi=None):
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": t,
+            "hw_valu": valu_from_profiles(key, workload, avg_s),
             "kernel": kname, "scheme": "symmetric" if scheme else "split",
             "target_blocks": blocks, "tail_pieces": tail,
             "avg_launch_ms": round(avg_s * 1e3, 5),
