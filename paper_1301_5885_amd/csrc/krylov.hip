@@ -134,15 +134,31 @@ __global__ __launch_bounds__(kBlock) void mgs_kernel(const Mol *__restrict__ mol
     const size_t len = 2 * (size_t)n;
     const double *red_in = M.red + ((i - 1) & 1) * kBlasBlocksMax;
     double *red_out = M.red + (i & 1) * kBlasBlocksMax;
-    const double h = sum_partials(red_in, nb, lds);
-    if (e.y == 0 && threadIdx.x == 0) M.H[(i - 1) * m + j] = h;
     const double *vp = M.V + (size_t)(i - 1) * len;
     const double *vn = i <= j ? M.V + (size_t)i * len : nullptr;
     double *w = M.w;
+    // the first element's operands are loaded before the partials are
+    // reduced, so the two memory latencies overlap
+    const int t0 = e.y * kBlock + threadIdx.x;
+    double p0 = 0.0, p1 = 0.0, w0 = 0.0, w1 = 0.0;
+    if (t0 < n) {
+        p0 = vp[t0];
+        p1 = vp[n + t0];
+        w0 = w[t0];
+        w1 = w[n + t0];
+    }
+    const double h = sum_partials(red_in, nb, lds);
+    if (e.y == 0 && threadIdx.x == 0) M.H[(i - 1) * m + j] = h;
     double s = 0.0;
-    for (int t = e.y * kBlock + threadIdx.x; t < n; t += nb * kBlock) {
-        const double wt = __builtin_fma(-h, vp[t], w[t]);
-        const double wb = __builtin_fma(-h, vp[n + t], w[n + t]);
+    for (int t = t0; t < n; t += nb * kBlock) {
+        if (t != t0) {
+            p0 = vp[t];
+            p1 = vp[n + t];
+            w0 = w[t];
+            w1 = w[n + t];
+        }
+        const double wt = __builtin_fma(-h, p0, w0);
+        const double wb = __builtin_fma(-h, p1, w1);
         w[t] = wt;
         w[n + t] = wb;
         if (vn)

@@ -1,19 +1,45 @@
-// Fixed-order workgroup reductions (wave64 shuffles, then LDS across the
-// four waves of a 256-thread workgroup).  The tree shape depends only on the
+// Fixed-order workgroup reductions (DPP lane moves within a wave64, then LDS
+// across the waves of the workgroup).  The tree shape depends only on the
 // workgroup size, so results are bitwise reproducible.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace gabi {
 
+// Fixed-order sum over the 64 lanes of a wave with DPP lane moves; the total
+// lands in lane 63.  Within each row of 16 lanes, shifts by 1, 2, 4 and 8
+// build the row prefix in lane 15 of the row; row_bcast:15 adds row 0 into
+// row 1 and row 2 into row 3, row_bcast:31 adds rows 0-1 into rows 2-3.
+// Lanes whose source is outside the pattern receive zero.  All 64 lanes must
+// be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+    const int hi =
+        __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo |
+                                          ((unsigned long long)(unsigned)hi << 32));
+}
+
+__device__ __forceinline__ double wave_total_lane63(double v) {
+    v += dpp_move<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Sum of v over the workgroup; the result is valid in every thread.
-// lds must hold blockDim.x / 64 doubles.  Contains __syncthreads().
+// lds must hold blockDim.x / 64 doubles.  Contains __syncthreads().  Every
+// thread of the workgroup must call it.
 __device__ __forceinline__ double block_sum(double v, double *lds) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    v = wave_total_lane63(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) lds[wave] = v;
+    if (lane == 63) lds[wave] = v;
     __syncthreads();
     double s = lds[0];
     const int nw = blockDim.x >> 6;
