@@ -312,9 +312,6 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
     // chunks of block J this tile covers: all four, or two for a half tile
     const int c0 = half == 2 ? 2 : 0, c1 = half == 1 ? 2 : kTile / 64;
     T top = T(0), bot = T(0);
-    T colt[kTile / 64], colb[kTile / 64];
-#pragma unroll
-    for (int c = 0; c < kTile / 64; ++c) colt[c] = colb[c] = T(0);
 #pragma unroll 1
     for (int c = c0; c < c1; ++c) {
         if (c * 64 >= cnt) break;
@@ -336,46 +333,53 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
             }
         } else {
             T ctop = T(0), cbot = T(0);
-#pragma unroll 8
-            for (int s = 0; s < 64; ++s) {
-                const T4 p = ca[-s], q = cb[-s];
-                const SymElem<T> b{p.x, p.y, p.z, q.x, q.y, q.z, p.w, q.w};
-                if constexpr (MIXED) {
-                    const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
-                    sym_f32(kc, a, b, top, bot, ctop, cbot);
-                } else {
-                    const PairConstF64 kc{M.kappa, M.eps, M.inv_eps};
-                    sym_f64(kc, a, b, top, bot, ctop, cbot);
-                }
-                ctop = wave_rotate(ctop);
-                cbot = wave_rotate(cbot);
-            }
-            // (registers are indexed by the chunk, so select rather than index)
+            // the next element is read one step ahead: step s reads element
+            // s + 1, which for the last step is entry 0 of the chunk copy (in
+            // bounds, unused).  Groups of 8 steps share one base address, so
+            // the reads take immediate offsets.
+            T4 p = ca[0], q = cb[0];
+            const T4 *pa = ca, *pb = cb;
+#pragma unroll 1
+            for (int g = 0; g < 8; ++g) {
+                pa -= 8;
+                pb -= 8;
 #pragma unroll
-            for (int cc = 0; cc < kTile / 64; ++cc)
-                if (cc == c) {
-                    colt[cc] = ctop;
-                    colb[cc] = cbot;
+                for (int u = 0; u < 8; ++u) {
+                    const T4 pn = pa[7 - u], qn = pb[7 - u];
+                    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the step
+                    const SymElem<T> b{p.x, p.y, p.z, q.x, q.y, q.z, p.w, q.w};
+                    if constexpr (MIXED) {
+                        const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
+                        sym_f32(kc, a, b, top, bot, ctop, cbot);
+                    } else {
+                        const PairConstF64 kc{M.kappa, M.eps, M.inv_eps};
+                        sym_f64(kc, a, b, top, bot, ctop, cbot);
+                    }
+                    ctop = wave_rotate(ctop);
+                    cbot = wave_rotate(cbot);
+                    p = pn;
+                    q = qn;
                 }
+            }
+            // once every wave is past chunk c, its (x, y, z, s) entries (both
+            // copies, 128 4-vectors) are free: they take each wave's 64 column
+            // sums of top and bot, so no registers carry them across chunks
+            static_assert(2 * kBlock <= 4 * 128, "column sums exceed a chunk's entries");
+            __syncthreads();
+            T *cs = reinterpret_cast<T *>(sa + c * 128);
+            cs[wave * 64 + lane] = ctop;
+            cs[kBlock + wave * 64 + lane] = cbot;
         }
     }
     if (I != J) {
-        // the staging area is free once every wave is past its last chunk; it
-        // holds exactly the 2 x 4 waves x 256 column sums
-        T *s_col = reinterpret_cast<T *>(s_stage);
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < kTile / 64; ++c) {
-            s_col[(2 * wave) * kTile + c * 64 + lane] = colt[c];
-            s_col[(2 * wave + 1) * kTile + c * 64 + lane] = colb[c];
-        }
         __syncthreads();
         if (tid < cnt && tid >= c0 * 64 && tid < c1 * 64) {
-            T ct = s_col[tid], cbs = s_col[kTile + tid];
+            const T *cs = reinterpret_cast<const T *>(sa + (tid >> 6) * 128);
+            T ct = cs[lane], cbs = cs[kBlock + lane];
 #pragma unroll
             for (int w = 1; w < kBlock / 64; ++w) {
-                ct += s_col[(2 * w) * kTile + tid];
-                cbs += s_col[(2 * w + 1) * kTile + tid];
+                ct += cs[w * 64 + lane];
+                cbs += cs[kBlock + w * 64 + lane];
             }
             part[(size_t)(2 * I) * n + jt + tid] = ct;
             part[(size_t)(2 * I + 1) * n + jt + tid] = cbs;
@@ -404,8 +408,8 @@ __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
     const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
     int *__restrict__ counter, int persistent, int skip) {
     using T4 = typename PairView<MIXED>::T4;
-    // two 4-vectors per element of block J, each chunk stored twice; reused
-    // for the column sums (2 x 4 waves x 256 values)
+    // two 4-vectors per element of block J, each chunk stored twice; the
+    // first copies also take the column sums (2 x 4 waves x 64 per chunk)
     __shared__ T4 s_stage[4 * kTile];
     __shared__ int s_next;
     int t = blockIdx.x;
