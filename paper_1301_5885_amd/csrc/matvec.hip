@@ -444,6 +444,33 @@ constexpr int kPairVariants = 3;  // split R = 2, split R = 1, symmetric
 // The finish also rearms the tile queues of the product it completes: the
 // pair launches of this precision start from a zero counter, and only the
 // finish that follows them reads or writes those counters in between.
+// st += slot 2p, sb += slot 2p + 1 of element i for p = p0 .. p1 - 1, added
+// in slot order.  The reads of eight slots are issued before their sums, so
+// a thread waits for memory once per eight slots rather than once per slot.
+template <typename P>
+__device__ __forceinline__ void sum_slots(const P *__restrict__ part, int n, int i, int p0,
+                                          int p1, double &st, double &sb) {
+    constexpr int kAhead = 8;
+    int p = p0;
+    for (; p + kAhead <= p1; p += kAhead) {
+        P a[kAhead], b[kAhead];
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            a[k] = part[(size_t)(2 * (p + k)) * n + i];
+            b[k] = part[(size_t)(2 * (p + k) + 1) * n + i];
+        }
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            st += (double)a[k];
+            sb += (double)b[k];
+        }
+    }
+    for (; p < p1; ++p) {
+        st += (double)part[(size_t)(2 * p) * n + i];
+        sb += (double)part[(size_t)(2 * p + 1) * n + i];
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
     const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision,
@@ -470,17 +497,10 @@ __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
         const int i = base + t;
         double st = 0.0, sb = 0.0;
         if (i < n) {
-            if (f32) {
-                for (int p = p0; p < p1; ++p) {
-                    st += (double)pf[(size_t)(2 * p) * n + i];
-                    sb += (double)pf[(size_t)(2 * p + 1) * n + i];
-                }
-            } else {
-                for (int p = p0; p < p1; ++p) {
-                    st += M.part[(size_t)(2 * p) * n + i];
-                    sb += M.part[(size_t)(2 * p + 1) * n + i];
-                }
-            }
+            if (f32)
+                sum_slots(pf, n, i, p0, p1, st, sb);
+            else
+                sum_slots(static_cast<const double *>(M.part), n, i, p0, p1, st, sb);
         }
         if (q > 0) {
             acc[0][q - 1][t] = st;
