@@ -138,14 +138,18 @@ __global__ __launch_bounds__(kBlock) void mgs_kernel(const Mol *__restrict__ mol
     const double *vn = i <= j ? M.V + (size_t)i * len : nullptr;
     double *w = M.w;
     // the first element's operands are loaded before the partials are
-    // reduced, so the two memory latencies overlap
+    // reduced, so the memory latencies overlap
     const int t0 = e.y * kBlock + threadIdx.x;
-    double p0 = 0.0, p1 = 0.0, w0 = 0.0, w1 = 0.0;
+    double p0 = 0.0, p1 = 0.0, w0 = 0.0, w1 = 0.0, n0 = 0.0, n1 = 0.0;
     if (t0 < n) {
         p0 = vp[t0];
         p1 = vp[n + t0];
         w0 = w[t0];
         w1 = w[n + t0];
+        if (vn) {
+            n0 = vn[t0];
+            n1 = vn[n + t0];
+        }
     }
     const double h = sum_partials(red_in, nb, lds);
     if (e.y == 0 && threadIdx.x == 0) M.H[(i - 1) * m + j] = h;
@@ -156,13 +160,17 @@ __global__ __launch_bounds__(kBlock) void mgs_kernel(const Mol *__restrict__ mol
             p1 = vp[n + t];
             w0 = w[t];
             w1 = w[n + t];
+            if (vn) {
+                n0 = vn[t];
+                n1 = vn[n + t];
+            }
         }
         const double wt = __builtin_fma(-h, p0, w0);
         const double wb = __builtin_fma(-h, p1, w1);
         w[t] = wt;
         w[n + t] = wb;
         if (vn)
-            s = __builtin_fma(wt, vn[t], __builtin_fma(wb, vn[n + t], s));
+            s = __builtin_fma(wt, n0, __builtin_fma(wb, n1, s));
         else
             s = __builtin_fma(wt, wt, __builtin_fma(wb, wb, s));
     }

@@ -148,6 +148,9 @@ __device__ __forceinline__ void pair_f32(
 //   bot_j += rinv^3 [ -u_j ((A/eps - 1) s_i + (B-3) t_i u_x rinv^2)
 //                     + (A-1) t_i n ],        u_x = d . nu_i, u_j = d . nu_j,
 // shares with the (i, j) term rho, 1/rho, E, A, B and the three dot products.
+// Both top terms are written with the shared factors P = (1-E) rinv and
+// Q = (eps A - 1) rinv^3:  top_i += P s_j + Q t_j u_j,
+// top_j += P s_i - Q t_i u_x.
 // The (i, j) term accumulates into top/bot, the (j, i) term into ctop/cbot.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -173,15 +176,15 @@ __device__ __forceinline__ void sym_f64(const PairConstF64 &c, const SymElem<dou
     const double ux = __builtin_fma(dx, a.nx, __builtin_fma(dy, a.ny, dz * a.nz));
     const double uj = __builtin_fma(dx, b.nx, __builtin_fma(dy, b.ny, dz * b.nz));
     const double nn = __builtin_fma(a.nx, b.nx, __builtin_fma(a.ny, b.ny, a.nz * b.nz));
+    const double P = __builtin_fma(-E, rinv, rinv), Q = a2 * rinv3;
     // target i, source j
     const double w = b.t * uj, qn = b.t * nn;
-    top = __builtin_fma(__builtin_fma(a2 * w, rinv2, __builtin_fma(-E, b.s, b.s)), rinv, top);
+    top = __builtin_fma(P, b.s, __builtin_fma(Q, w, top));
     const double k3 = __builtin_fma(a1, b.s, -B3r2 * w);
     bot = __builtin_fma(__builtin_fma(ux, k3, __builtin_fma(A, qn, -qn)), rinv3, bot);
     // target j, source i
     const double wm = a.t * ux, qj = a.t * nn;
-    ctop = __builtin_fma(__builtin_fma(-(a2 * wm), rinv2, __builtin_fma(-E, a.s, a.s)), rinv,
-                         ctop);
+    ctop = __builtin_fma(P, a.s, __builtin_fma(-Q, wm, ctop));
     const double k3j = __builtin_fma(a1, a.s, B3r2 * wm);
     cbot = __builtin_fma(__builtin_fma(-uj, k3j, __builtin_fma(A, qj, -qj)), rinv3, cbot);
 }
@@ -205,13 +208,13 @@ __device__ __forceinline__ void sym_f32(const PairConstF32 &c, const SymElem<flo
     const float ux = __builtin_fmaf(dx, a.nx, __builtin_fmaf(dy, a.ny, dz * a.nz));
     const float uj = __builtin_fmaf(dx, b.nx, __builtin_fmaf(dy, b.ny, dz * b.nz));
     const float nn = __builtin_fmaf(a.nx, b.nx, __builtin_fmaf(a.ny, b.ny, a.nz * b.nz));
+    const float P = __builtin_fmaf(-E, rinv, rinv), Q = a2 * rinv3;
     const float w = b.t * uj, qn = b.t * nn;
-    top = __builtin_fmaf(__builtin_fmaf(a2 * w, rinv2, __builtin_fmaf(-E, b.s, b.s)), rinv, top);
+    top = __builtin_fmaf(P, b.s, __builtin_fmaf(Q, w, top));
     const float k3 = __builtin_fmaf(a1, b.s, -B3r2 * w);
     bot = __builtin_fmaf(__builtin_fmaf(ux, k3, __builtin_fmaf(A, qn, -qn)), rinv3, bot);
     const float wm = a.t * ux, qj = a.t * nn;
-    ctop = __builtin_fmaf(__builtin_fmaf(-(a2 * wm), rinv2, __builtin_fmaf(-E, a.s, a.s)), rinv,
-                          ctop);
+    ctop = __builtin_fmaf(P, a.s, __builtin_fmaf(-Q, wm, ctop));
     const float k3j = __builtin_fmaf(a1, a.s, B3r2 * wm);
     cbot = __builtin_fmaf(__builtin_fmaf(-uj, k3j, __builtin_fmaf(A, qj, -qj)), rinv3, cbot);
 }

@@ -112,8 +112,17 @@ __global__ __launch_bounds__(kBlock) void reaction_finish_kernel(const Mol *__re
     const int nc = M.nc;
     double e = 0.0;
     for (int k = threadIdx.x; k < nc; k += kBlock) {
+        // in split order; eight reads are issued ahead of their sums
         double s = 0.0;
-        for (int sp = 0; sp < M.rx_splits; ++sp) s += M.phi_part[(size_t)sp * nc + k];
+        int sp = 0;
+        for (; sp + 8 <= M.rx_splits; sp += 8) {
+            double a[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[q] = M.phi_part[(size_t)(sp + q) * nc + k];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s += a[q];
+        }
+        for (; sp < M.rx_splits; ++sp) s += M.phi_part[(size_t)sp * nc + k];
         M.phi[k] = s;
         e = __builtin_fma(M.chg[k].w, s, e);
     }
