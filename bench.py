@@ -203,6 +203,42 @@ def cpu_baseline(problem, seconds):
             "sample": f"{reps} {what}, {elapsed:.1f} s wall"}
 
 
+def warm_sequence(ctx, gabi, p, steps):
+    """Solves along a sequence of nearby problems, the many-solves use case:
+    every charge moves by an N(0, (0.05 A)^2) step per solve.  Mixed IR at the
+    bench tolerance, from zero against from the previous solution (kept on
+    the device, gabi_solve_opts.x0_previous); wall time per solve includes
+    the charge upload, the solve and the energy.  Not the headline."""
+    import numpy as np
+    rng = np.random.default_rng(77)
+    P = [p.pos.copy()]
+    for _ in range(steps):
+        P.append(P[-1] + rng.normal(scale=0.05, size=p.pos.shape))
+    runs = {}
+    for key, previous in (("cold", 0), ("warm", 1)):
+        ctx.set_charges(P[0], p.q)
+        ctx.solve(tol=TOL, mode=gabi.SOLVE_MIXED_IR)
+        its, energies, seconds = [], [], 0.0
+        for Pk in P[1:]:
+            t0 = time.perf_counter()
+            ctx.set_charges(Pk, p.q)
+            _, info = ctx.solve(tol=TOL, mode=gabi.SOLVE_MIXED_IR, x0_previous=previous)
+            energies.append(ctx.energy())
+            seconds += time.perf_counter() - t0
+            if not info["converged"]:
+                raise RuntimeError(f"{key} sequence solve did not converge: {info}")
+            its.append(info["iterations"])
+        runs[key] = (seconds, its, energies)
+    (tc, ic, ec), (tw, iw, ew) = runs["cold"], runs["warm"]
+    return {"steps": steps,
+            "perturbation": "every charge moved by N(0, (0.05 A)^2) per solve",
+            "cold_ms_per_solve": round(1e3 * tc / steps, 3),
+            "warm_ms_per_solve": round(1e3 * tw / steps, 3),
+            "cold_iterations_per_solve": sum(ic) / steps,
+            "warm_iterations_per_solve": sum(iw) / steps,
+            "max_energy_rel_diff_warm_vs_cold": max(abs(a / b - 1) for a, b in zip(ew, ec))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +251,9 @@ def main():
                     help="requests of the serving stream to serve after the single-solve "
                          "timing (0: skip; the stream has 512)")
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--sequence-steps", type=int, default=8,
+                    help="nearby problems solved cold and warm-started after the timing "
+                         "(0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run one device copy of this many MiB "
                          "(a kernel of known traffic for scaling HBM counters)")
@@ -296,6 +335,10 @@ def main():
         },
         "speedup_mixed_over_fp64": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3),
     }
+    if args.sequence_steps > 0:
+        log(f"[bench] warm-started sequence: {args.sequence_steps} nearby problems")
+        line["warm_sequence"] = warm_sequence(ctx, gabi, p, args.sequence_steps)
+        log(f"[bench] sequence: {line['warm_sequence']}")
     ctx.close()
     if serve_problems is not None:
         log(f"[bench] serving {args.serve_requests} requests")

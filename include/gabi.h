@@ -86,6 +86,14 @@ typedef struct {
     int32_t max_outer; /* MIXED_IR: cap on refinement steps (20)              */
     int32_t use_graph; /* replay each round (cycle, update, residual) as a
                           captured HIP graph when timing is off (1)           */
+    int32_t x0_previous; /* gabi_solve/gabi_solve_dev with a null x0: 1 starts
+                          from the solution this context's last solve
+                          returned, which stays on the device while the
+                          surface keeps its number of elements (charges,
+                          parameters and element data may have changed since:
+                          the warm start of a sequence of nearby problems,
+                          Section 4); 0, or no such solution, starts from
+                          zero.  Batch and server calls ignore it (0)         */
 } gabi_solve_opts;
 
 typedef struct {
@@ -97,6 +105,8 @@ typedef struct {
     double rel_residual;  /* explicit FP64 ||b - A u|| / ||b|| at exit        */
     int32_t converged;    /* 1 if rel_residual <= tol                         */
     double seconds;       /* wall time of the call                            */
+    int32_t warm_start;   /* 1 if the initial guess was not zero (x0 given or
+                             the previous solution, see x0_previous)          */
 } gabi_solve_info;
 
 /* Fill opts with the defaults listed above.                                */

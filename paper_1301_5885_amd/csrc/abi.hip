@@ -170,6 +170,10 @@ int opts_check(const gabi_solve_opts *in, gabi_solve_opts *o, std::string &msg) 
         msg = "need 0 < inner_tol < 1 and max_outer >= 1";
         return GABI_EINVAL;
     }
+    if (o->x0_previous != 0 && o->x0_previous != 1) {
+        msg = "x0_previous must be 0 or 1";
+        return GABI_EINVAL;
+    }
     return GABI_OK;
 }
 
@@ -265,6 +269,7 @@ int ensure_slot(gabi_ctx *ctx, int m) {
         ctx->m_alloc = m;
         ctx->geom_dirty = ctx->chg_dirty = true;
         ctx->have_solution = false;
+        ctx->prev_solution = false;
         ctx->batch_dirty = true;
     }
     if (ctx->geom_dirty) {
@@ -340,6 +345,7 @@ void gabi_default_opts(gabi_solve_opts *o) {
     o->inner_tol = 1e-5;
     o->max_outer = 20;
     o->use_graph = 1;
+    o->x0_previous = 0;
 }
 
 int gabi_create(gabi_ctx **out, int device) {
@@ -580,9 +586,16 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
     Timer t = make_timer(ctx);
     const bool graph = o.use_graph && !ctx->timing;
     const size_t bytes = sizeof(double) * 2 * ctx->n;
+    // the previous solution is still in the slot's solution buffer: nothing
+    // but a solve writes it, and a new slot clears prev_solution
+    const bool previous = !x0 && o.x0_previous && ctx->prev_solution;
     if (x0)
         GABI_HIP(ctx, hipMemcpyAsync(sl.mol.res_x, x0, bytes, x0_kind, ctx->stream));
-    enqueue_init(b, ctx->stream, x0 != nullptr, &t);
+    else if (previous)
+        GABI_HIP(ctx, hipMemcpyAsync(sl.mol.res_x, sl.mol.sol, bytes, hipMemcpyDeviceToDevice,
+                                     ctx->stream));
+    const bool warm = x0 != nullptr || previous;
+    enqueue_init(b, ctx->stream, warm, &t);
     if ((rc = read_status(ctx))) return rc;
     int rounds = 0;
     for (;;) {
@@ -601,7 +614,7 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
     gabi_solve_info out{};
     out.iterations = st.iters;
     out.restarts = rounds;
-    const int64_t extra = x0 ? 1 : 0;
+    const int64_t extra = warm ? 1 : 0;
     if (mode == kModeMixed) {
         out.matvecs_fp32 = st.iters;
         out.matvecs_fp64 = rounds + extra;
@@ -612,8 +625,10 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
     out.rel_residual = st.beta0 > 0 ? st.rnorm / st.beta0 : 0.0;
     out.converged = st.converged;
     out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    out.warm_start = warm ? 1 : 0;
     if (info) *info = out;
     ctx->have_solution = true;
+    ctx->prev_solution = true;
     return out.converged ? GABI_OK : GABI_NOT_CONVERGED;
 }
 

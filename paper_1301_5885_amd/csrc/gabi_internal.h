@@ -201,6 +201,7 @@ struct gabi_ctx {
     int64_t slot_n = -1, slot_nc = -1;
     int m_alloc = 0;
     bool charges_set = false, params_set = false, have_solution = false;
+    bool prev_solution = false;  // the slot's solution buffer holds a solve's result
     double eps1 = 1.0, eps2 = 80.0, kappa = 0.0;
     std::vector<double> host_centroids;  // 3n, for validation
     std::vector<double> host_charges;    // 4nc

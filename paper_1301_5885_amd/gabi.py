@@ -57,14 +57,16 @@ class GabiError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
                 ("mode", C.c_int32), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int32), ("use_graph", C.c_int32)]
+                ("max_outer", C.c_int32), ("use_graph", C.c_int32),
+                ("x0_previous", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("matvecs_fp64", C.c_int64),
                 ("matvecs_fp32", C.c_int64), ("restarts", C.c_int64),
                 ("outer", C.c_int64), ("rel_residual", C.c_double),
-                ("converged", C.c_int32), ("seconds", C.c_double)]
+                ("converged", C.c_int32), ("seconds", C.c_double),
+                ("warm_start", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

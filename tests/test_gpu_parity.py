@@ -211,6 +211,35 @@ def test_solve_mixed_ir_energy_gate(ctx, name):
         assert rel(u, u_tight) <= 1e-6
 
 
+@pytest.mark.parametrize("workload", ["kirkwood", "star"])
+def test_full_size_solves_against_golden(ctx, workload):
+    """Both solvers on the full-size workload against the tightly converged
+    FP64 oracle energy stored in tests/golden (written by make_golden.py).
+    The FP64 solver at rel. residual 1e-8 must also take the oracle's GMRES
+    iteration count at that tolerance (within one) and land on the oracle's
+    1e-8 energy."""
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           f"{workload}_reference.json")) as f:
+        ref = json.load(f)
+    p = config_problem(workload)
+    log(f"[golden] {workload} N={p.n} Nc={p.nc}")
+    load(ctx, p.V, p.F, p.pos, p.q, p.eps1, p.eps2, p.kappa)
+    E_tight = ref["energy_kcal_per_mol"]
+    u, info = ctx.solve(tol=1e-8)
+    E = ctx.energy()
+    log(f"    fp64 {info} E={E} rel={abs(E / E_tight - 1):.3e}")
+    assert info["converged"]
+    assert abs(info["iterations"] - ref["tol_1e-8"]["gmres"]["iterations"]) <= 1
+    assert abs(E / ref["tol_1e-8"]["energy_kcal_per_mol"] - 1) <= 1e-9
+    assert abs(E / E_tight - 1) <= 1e-6
+    u, info = ctx.solve(tol=1e-8, mode=gabi.SOLVE_MIXED_IR)
+    E = ctx.energy()
+    log(f"    mixed {info} E={E} rel={abs(E / E_tight - 1):.3e}")
+    assert info["converged"]
+    assert abs(E / E_tight - 1) <= 1e-6
+
+
 def test_determinism_and_device_entry_points(ctx):
     import torch
     V, F, pos, q = CASES["star_4500_ragged"]()
