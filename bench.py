@@ -198,9 +198,27 @@ def cpu_baseline(problem, seconds):
         if time.perf_counter() - t0 >= seconds:
             break
     elapsed = time.perf_counter() - t0
-    return {"value": round(reps * unit_pairs / elapsed / 1e9, 5), "unit": "Gpair-kernels/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{reps} {what}, {elapsed:.1f} s wall"}
+    out = {"value": round(reps * unit_pairs / elapsed / 1e9, 5), "unit": "Gpair-kernels/s",
+           "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{reps} {what}, {elapsed:.1f} s wall"}
+    # the same oracle on one core, to set beside single-core CPU figures
+    cores = oracle.num_threads()
+    nrows1 = int(max(16, min(2 * el.n, seconds * 0.25 * 0.08e9 / (el.n - 1))))
+    rows1 = np.random.default_rng(2).choice(2 * el.n, nrows1, replace=False)
+    oracle.set_num_threads(1)
+    try:
+        reps1, t1 = 0, time.perf_counter()
+        while True:
+            oracle.matvec_rows(el, u, rows1, *args)
+            reps1 += 1
+            if time.perf_counter() - t1 >= seconds * 0.25:
+                break
+        el1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(cores)
+    out["one_core"] = {"value": round(reps1 * nrows1 * (el.n - 1) / el1 / 1e9, 5),
+                       "sample": f"{reps1} samples of {nrows1} random rows, {el1:.1f} s wall"}
+    return out
 
 
 def warm_sequence(ctx, gabi, p, steps):

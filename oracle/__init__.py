@@ -82,11 +82,17 @@ def _declare(lib):
     lib.oracle_energy.argtypes = ops + [_dp, _i64, _dp, _dp, _dp, _dp]
     lib.oracle_energy.restype = C.c_double
     lib.oracle_num_threads.restype = C.c_int
+    lib.oracle_set_num_threads.argtypes = [C.c_int]
 
 
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads of later OpenMP loops (timing runs only; no effect on results)."""
+    _load().oracle_set_num_threads(int(t))
 
 
 def _p(a):

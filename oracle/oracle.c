@@ -55,6 +55,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Sets the threads of later OpenMP regions (t >= 1; for timing runs).       */
+void oracle_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    if (t >= 1) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Element data from a triangle mesh (Section 2.2).                          */
 /* ------------------------------------------------------------------------ */
