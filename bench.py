@@ -110,21 +110,33 @@ def golden_energy(workload):
 
 
 def run_solver(ctx, gabi, torch, u, mode, steps, warmup, pairs):
+    """Two timed passes of `steps` solves (each solve includes its energy):
+    the first with kernel timing off gives the throughput; the second, the
+    same solves with HIP events recorded around every pair-kernel launch
+    (event-record nodes inside the replayed round graphs, which add about
+    3 us per record), gives the kernel durations for the roofline."""
     for _ in range(warmup):
         ctx.solve_dev(u, tol=TOL, mode=mode)
         ctx.energy_dev(None)
     torch.cuda.synchronize()
-    for prec in (gabi.FP64, gabi.FP32_PAIR):
-        ctx.kernel_time(prec, reset=True)
-    ctx.set_kernel_timing(True)
     infos, energies = [], []
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         infos.append(ctx.solve_dev(u, tol=TOL, mode=mode))
         energies.append(ctx.energy_dev(None))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    for prec in (gabi.FP64, gabi.FP32_PAIR):
+        ctx.kernel_time(prec, reset=True)
+    ctx.set_kernel_timing(True)
+    timed_infos = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        timed_infos.append(ctx.solve_dev(u, tol=TOL, mode=mode))
+        ctx.energy_dev(None)
+    torch.cuda.synchronize()
+    elapsed_timed = time.perf_counter() - t1
     ctx.set_kernel_timing(False)
     kt = {}
     for prec, key in ((gabi.FP64, "fp64"), (gabi.FP32_PAIR, "fp32")):
@@ -138,17 +150,21 @@ def run_solver(ctx, gabi, torch, u, mode, steps, warmup, pairs):
         "gpairs_per_s": (p64 + p32) * pairs / elapsed / 1e9,
         "solves_per_s": steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
+        "timed_pass_ms_per_step": 1e3 * elapsed_timed / steps,
+        "timed_products_fp64": sum(i["matvecs_fp64"] for i in timed_infos),
+        "timed_products_fp32": sum(i["matvecs_fp32"] for i in timed_infos),
         "kernel_total_ms": {k: v[0] * v[1] for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
     }
 
 
 def roofline(res, key, n, workload, gabi=None):
-    products = res["products_fp32" if key == "fp32" else "products_fp64"]
+    products = res["timed_products_fp32" if key == "fp32" else "timed_products_fp64"]
     if products == 0:
         return None
-    # every launch is timed; launches skipped after an early stop of a cycle
-    # last a few microseconds and are charged to the real products
+    # every launch of the timed pass is timed; launches skipped after an early
+    # stop of a cycle last a few microseconds and are charged to the real
+    # products
     avg_s = res["kernel_total_ms"][key] / products / 1e3
     flop = FLOP_PER_PAIR * n * (n - 1)
     achieved = flop / avg_s / 1e12
@@ -167,7 +183,10 @@ def roofline(res, key, n, workload, gabi=None):
             "kernel": kname, "scheme": "symmetric" if scheme else "split",
             "target_blocks": blocks, "tail_pieces": tail,
             "avg_launch_ms": round(avg_s * 1e3, 5),
-            "flop_per_launch": flop}
+            "flop_per_launch": flop,
+            "timing": "HIP events around every pair-kernel launch in a second timed pass "
+                      f"of the same solves ({res['timed_pass_ms_per_step']:.3f} ms/step with "
+                      "the event records)"}
 
 
 def cpu_baseline(problem, seconds):

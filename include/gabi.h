@@ -85,7 +85,8 @@ typedef struct {
                           current residual (1e-5)                             */
     int32_t max_outer; /* MIXED_IR: cap on refinement steps (20)              */
     int32_t use_graph; /* replay each round (cycle, update, residual) as a
-                          captured HIP graph when timing is off (1)           */
+                          captured HIP graph (1); with kernel timing on, the
+                          captured round records events around its products */
     int32_t x0_previous; /* gabi_solve/gabi_solve_dev with a null x0: 1 starts
                           from the solution this context's last solve
                           returned, which stays on the device while the
@@ -201,8 +202,9 @@ int64_t gabi_device_bytes(const gabi_ctx *ctx);
 
 /* Average device duration (milliseconds) of the pair-kernel launches of
  * products made since the last reset, measured with HIP events around each
- * launch on the context's stream when timing is enabled; count receives
- * the number of launches.  Timing adds two event records per product.     */
+ * launch on the context's stream when timing is enabled (event-record nodes
+ * inside a captured round); count receives the number of launches.  Timing
+ * adds two event records per product.                                      */
 int gabi_set_kernel_timing(gabi_ctx *ctx, int enable);
 int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
                      int64_t *count, int reset);

@@ -584,7 +584,7 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
     if ((rc = sync_batch(ctx))) return rc;
     Batch &b = ctx->batch;
     Timer t = make_timer(ctx);
-    const bool graph = o.use_graph && !ctx->timing;
+    const bool graph = o.use_graph != 0;
     const size_t bytes = sizeof(double) * 2 * ctx->n;
     // the previous solution is still in the slot's solution buffer: nothing
     // but a solve writes it, and a new slot clears prev_solution
@@ -605,6 +605,7 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
         if ((rc = run_round(b, ctx->stream, ctx->capture, &t, graph, msg)))
             return fail(ctx, rc, msg);
         if ((rc = read_status(ctx))) return rc;
+        if (graph && ctx->timing) graph_round_times(b, ctx->total_ms, ctx->count);
         ++rounds;
     }
     enqueue_finalize(b, ctx->stream);  // solution to sol, reaction potential, energy

@@ -178,10 +178,16 @@ struct Batch {
     // captured round (hipGraph), valid while the batch is unchanged
     hipGraphExec_t graph = nullptr;
     bool graph_valid = false;
+    // a round captured with timing holds event-record nodes around every
+    // product launch; these are their events, whose timestamps each replay
+    // overwrites
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> graph_events[2];
+    bool graph_timed = false;
 };
 
 int batch_build(Batch &b, hipStream_t stream, std::string &err);
 void batch_free(Batch &b);
+void release_graph(Batch &b);  // the captured round and its events
 
 }  // namespace gabi
 
@@ -268,6 +274,7 @@ void enqueue_gather(Batch &b, hipStream_t s);
 void enqueue_finalize(Batch &b, hipStream_t s);
 int run_round(Batch &b, hipStream_t s, hipStream_t capture, const Timer *t,
               bool use_graph, std::string &err);
+void graph_round_times(const Batch &b, double *ms, int64_t *count);
 void set_solve_targets(Slot &slot, double tol, double inner_tol, int maxit);
 
 }  // namespace gabi

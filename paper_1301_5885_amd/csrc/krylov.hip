@@ -307,24 +307,51 @@ void enqueue_finalize(Batch &b, hipStream_t s) {
     launch_reaction(b, s, true);
 }
 
-// One round, eager or as a replay of the captured graph of this batch.
+// One round, eager or as a replay of the captured graph of this batch.  A
+// timed round is captured with event records around its product launches
+// (Batch::graph_events; read them with graph_round_times once the replay has
+// completed); a change of the timing choice captures the round again.
 int run_round(Batch &b, hipStream_t s, hipStream_t capture, const Timer *t,
               bool use_graph, std::string &err) {
-    if (use_graph && !t && capture) {
-        if (!b.graph_valid) {
+    const bool timed = t && (t->pending[0] || t->pending[1]);
+    {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            err = std::string("an earlier device call failed: ") + hipGetErrorString(e);
+            return GABI_EDEVICE;
+        }
+    }
+    if (use_graph && capture) {
+        if (!b.graph_valid || b.graph_timed != timed) {
+            release_graph(b);
+            Timer gt;
+            if (timed) {
+                gt.pending[0] = &b.graph_events[0];
+                gt.pending[1] = &b.graph_events[1];
+            }
             hipGraph_t g = nullptr;
+            const char *step = "begin capture";
             hipError_t e = hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed);
             if (e == hipSuccess) {
-                enqueue_round(b, capture, nullptr);
+                enqueue_round(b, capture, timed ? &gt : nullptr);
+                const hipError_t ec = hipGetLastError();  // a launch or record in capture
                 e = hipStreamEndCapture(capture, &g);
+                step = "capture";
+                if (e == hipSuccess) e = ec;
             }
-            if (e == hipSuccess) e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) {
+                step = "instantiate";
+                e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+            }
             if (g) (void)hipGraphDestroy(g);
             if (e != hipSuccess) {
-                err = std::string("graph capture of a round failed: ") + hipGetErrorString(e);
+                release_graph(b);
+                err = std::string("graph ") + step + " of a round failed: " +
+                      hipGetErrorString(e);
                 return GABI_EDEVICE;
             }
             b.graph_valid = true;
+            b.graph_timed = timed;
         }
         hipError_t e = hipGraphLaunch(b.graph, s);
         if (e != hipSuccess) {
@@ -340,6 +367,22 @@ int run_round(Batch &b, hipStream_t s, hipStream_t capture, const Timer *t,
         return GABI_EDEVICE;
     }
     return GABI_OK;
+}
+
+// Adds the product-launch times of the last replay of a timed captured round
+// (index 0 FP64, 1 FP32-pair); the replay must have completed.
+void graph_round_times(const Batch &b, double *ms, int64_t *count) {
+    if (!b.graph_valid || !b.graph_timed) return;
+    for (int p = 0; p < 2; ++p)
+        for (const auto &ev : b.graph_events[p]) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, ev.first, ev.second) == hipSuccess) {
+                ms[p] += t;
+                count[p] += 1;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
 }
 
 }  // namespace gabi

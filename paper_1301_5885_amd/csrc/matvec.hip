@@ -572,6 +572,25 @@ static void pair_group(Batch &b, hipStream_t s, const int4 *tiles, int ntiles, i
                            tiles, ntiles, counter, (int)b.persistent, (int)skip);
 }
 
+// Records e on s; on a stream under capture the record becomes an
+// event-record node of the graph (added by hand after the nodes captured so
+// far), so that every replay timestamps it.
+static void record_event(hipEvent_t e, hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    if (hipStreamGetCaptureInfo_v2(s, &st, &id, &g, &deps, &nd) != hipSuccess ||
+        st != hipStreamCaptureStatusActive) {
+        (void)hipEventRecord(e, s);
+        return;
+    }
+    hipGraphNode_t node = nullptr;
+    if (hipGraphAddEventRecordNode(&node, g, deps, nd, e) == hipSuccess)
+        (void)hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
+}
+
 void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer *t) {
     const bool mixed = precision != GABI_FP64;
     const int *cnt = mixed ? b.n_tiles32 : b.n_tiles64;
@@ -583,7 +602,7 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
             e0 = e1 = nullptr;
         } else {
-            (void)hipEventRecord(e0, s);
+            record_event(e0, s);
         }
     }
     int *c = b.d_counter + (mixed ? 4 : 0);
@@ -598,7 +617,7 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
         pair_group<false, 0>(b, s, t2, cnt[2], c + 2, b.grid64[2], skip);
     }
     if (e0 && e1) {
-        (void)hipEventRecord(e1, s);
+        record_event(e1, s);
         t->pending[pi]->push_back({e0, e1});
     }
 }

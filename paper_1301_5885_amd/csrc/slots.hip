@@ -288,10 +288,22 @@ int64_t next_slot_uid() {
 }
 
 // ---------------------------------------------------------------- batches
-void batch_free(Batch &b) {
+void release_graph(Batch &b) {
     if (b.graph) (void)hipGraphExecDestroy(b.graph);
     b.graph = nullptr;
     b.graph_valid = false;
+    b.graph_timed = false;
+    for (auto &v : b.graph_events) {
+        for (auto &ev : v) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+        v.clear();
+    }
+}
+
+void batch_free(Batch &b) {
+    release_graph(b);
     if (b.d_mem) (void)hipFree(b.d_mem);
     if (b.h_pinned) (void)hipHostFree(b.h_pinned);
     b.d_mem = nullptr;
@@ -378,9 +390,7 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     const int64_t o_st = al(o_cnt + 256);
     const int64_t total = al(o_st + (int64_t)sizeof(KrylovStatus) * std::max(1, nm));
 
-    if (b.graph) (void)hipGraphExecDestroy(b.graph);
-    b.graph = nullptr;
-    b.graph_valid = false;
+    release_graph(b);
     if (total > b.cap_bytes || !b.d_mem) {
         if (b.d_mem) (void)hipFree(b.d_mem);
         if (b.h_pinned) (void)hipHostFree(b.h_pinned);
