@@ -186,8 +186,9 @@ int gabi_solve_dev(gabi_ctx *ctx, const gabi_solve_opts *opts,
 
 /* Electrostatic solvation energy (Section 2.3, eq. (solvation_energy)) in
  * kcal/mol for the surface values u (length 2N, host for gabi_energy,
- * device for gabi_energy_dev), or for the last solution if u is null.
- * Always evaluated in FP64.                                                 */
+ * device for gabi_energy_dev), or for the last solution if u is null (then
+ * the value the solve's final step evaluated is returned without device
+ * work).  Always evaluated in FP64.                                         */
 int gabi_energy(gabi_ctx *ctx, const double *u, double *e_kcal_per_mol);
 int gabi_energy_dev(gabi_ctx *ctx, const double *u_dev,
                     double *e_kcal_per_mol);

@@ -629,6 +629,8 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
     out.warm_start = warm ? 1 : 0;
     if (info) *info = out;
     ctx->have_solution = true;
+    ctx->solution_energy = st.energy;  // enqueue_finalize evaluated it
+    ctx->solution_energy_valid = true;
     ctx->prev_solution = true;
     return out.converged ? GABI_OK : GABI_NOT_CONVERGED;
 }
@@ -648,7 +650,18 @@ static int energy_impl(gabi_ctx *ctx, const void *u, hipMemcpyKind kind, double 
                        double *phi_host) {
     int rc = prepare(ctx, true, 0);
     if (rc) return rc;
+    if (!u && ctx->have_solution && ctx->solution_energy_valid) {
+        // the solve's final step left E and phi_reac of its solution
+        if (phi_host && ctx->nc) {
+            GABI_HIP(ctx, hipMemcpyAsync(phi_host, ctx->slot.mol.phi, sizeof(double) * ctx->nc,
+                                         hipMemcpyDeviceToHost, ctx->stream));
+            GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        if (e) *e = ctx->solution_energy;
+        return GABI_OK;
+    }
     if (u) {
+        ctx->solution_energy_valid = false;  // phi_reac and E now belong to u
         GABI_HIP(ctx, hipMemcpyAsync(ctx->slot.mol.u, u, sizeof(double) * 2 * ctx->n, kind,
                                      ctx->stream));
     } else if (!ctx->have_solution) {
@@ -660,6 +673,10 @@ static int energy_impl(gabi_ctx *ctx, const void *u, hipMemcpyKind kind, double 
                                      hipMemcpyDeviceToHost, ctx->stream));
     if ((rc = read_status(ctx))) return rc;
     if (e) *e = ctx->batch.h_status[0].energy;
+    if (!u) {
+        ctx->solution_energy = ctx->batch.h_status[0].energy;
+        ctx->solution_energy_valid = true;
+    }
     return GABI_OK;
 }
 

@@ -208,6 +208,11 @@ struct gabi_ctx {
     int m_alloc = 0;
     bool charges_set = false, params_set = false, have_solution = false;
     bool prev_solution = false;  // the slot's solution buffer holds a solve's result
+    // energy and reaction potential (in the slot) of the last solution, as the
+    // solve's final step computed them; valid while have_solution holds and
+    // no energy of another u has been evaluated since
+    bool solution_energy_valid = false;
+    double solution_energy = 0.0;
     double eps1 = 1.0, eps2 = 80.0, kappa = 0.0;
     std::vector<double> host_centroids;  // 3n, for validation
     std::vector<double> host_charges;    // 4nc

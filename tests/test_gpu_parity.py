@@ -240,6 +240,23 @@ def test_full_size_solves_against_golden(ctx, workload):
     assert abs(E / E_tight - 1) <= 1e-6
 
 
+def test_energy_of_last_solution_reuses_the_solve(ctx):
+    """The solve's last step evaluates E and phi_reac of its solution;
+    energy()/reaction_potential() without u return those, and they equal a
+    fresh evaluation of the same u (same kernels, same input)."""
+    V, F, pos, q = CASES["star_1620_ragged"]()
+    el = load(ctx, V, F, pos, q)
+    u, _ = ctx.solve(tol=1e-8)
+    E0 = ctx.energy()
+    phi0 = ctx.reaction_potential()
+    assert ctx.energy(u) == E0
+    assert np.array_equal(ctx.reaction_potential(u), phi0)
+    assert ctx.energy(2.0 * u) != E0
+    assert ctx.energy() == E0   # evaluated again from the stored solution
+    assert np.array_equal(ctx.reaction_potential(), phi0)
+    assert abs(E0 / oracle.energy(el, u, pos, q) - 1) <= 1e-12
+
+
 def test_determinism_and_device_entry_points(ctx):
     import torch
     V, F, pos, q = CASES["star_4500_ragged"]()
