@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "arnoldi.h"
 #include "gabi_internal.h"
 #include "reduce.h"
 
@@ -49,12 +50,6 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const Mol *__restrict__ mo
         dst[i] = src[i];
         dst[n + i] = src[n + i];
     }
-}
-
-__device__ __forceinline__ double sum_partials(const double *red, int nb, double *lds) {
-    double v = 0.0;
-    for (int t = threadIdx.x; t < nb; t += kBlock) v += red[t];
-    return block_sum(v, lds);
 }
 
 // partials of ||rhs||^2
@@ -178,36 +173,14 @@ __global__ __launch_bounds__(kBlock) void mgs_kernel(const Mol *__restrict__ mol
     if (threadIdx.x == 0) red_out[e.y] = s;
 }
 
-// one workgroup per molecule: h_{j+1,j} = ||w||, rotations, estimate, stop
+// one workgroup per molecule: the Givens step that closes step j (the last
+// step of a cycle; the earlier ones run inside the next step's prep)
 __global__ __launch_bounds__(kBlock) void givens_kernel(const Mol *__restrict__ mols, int j) {
     __shared__ double lds[kBlock / 64];
     const Mol &M = mols[blockIdx.x];
-    KrylovStatus *st = M.st;
-    if (st->done) return;
-    const int m = M.m;
+    if (M.st->done) return;
     const double hn = sqrt(sum_partials(M.red + ((j + 1) & 1) * kBlasBlocksMax, M.nb, lds));
-    if (threadIdx.x != 0) return;
-    double *H = M.H, *cs = M.cs, *sn = M.sn, *g = M.g;
-    M.hn[j] = hn;
-    H[(j + 1) * m + j] = hn;
-    for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], c = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * c;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-    }
-    const double a = H[j * m + j], c = H[(j + 1) * m + j];
-    const double den = hypot(a, c);
-    cs[j] = a / den;
-    sn[j] = c / den;
-    H[j * m + j] = den;
-    H[(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    st->iters += 1;
-    st->k = j + 1;
-    st->gabs = fabs(g[j + 1]);
-    if (fabs(g[j + 1]) / st->beta <= st->tol || st->iters >= st->maxit || hn == 0.0)
-        st->done = 1;
+    if (threadIdx.x == 0) givens_step(M, j, hn);
 }
 
 // upd_dst += V y with H(0:k,0:k) y = g(0:k); every workgroup solves the small
@@ -279,14 +252,16 @@ void enqueue_round(Batch &b, hipStream_t s, const Timer *t) {
     const int prec = b.mode == kModeMixed ? GABI_FP32_PAIR : GABI_FP64;
     const int m = b.slots.empty() ? 0 : b.slots[0]->mol.m;
     for (int j = 0; j < m; ++j) {
+        // the prep of step j > 0 also runs the Givens step that closes j - 1
         launch_prep(b, s, prec, j == 0 ? kPrepCycle0 : kPrepCycleJ, j, true);
         launch_pair(b, s, prec, true, t);
         launch_finish(b, s, prec, kFinishDot, j, true);
         for (int i = 1; i <= j + 1; ++i)
             hipLaunchKernelGGL(mgs_kernel, dim3(b.n_blas), dim3(kBlock), 0, s, b.d_mols,
                                b.d_blas, i, j);
-        hipLaunchKernelGGL(givens_kernel, dim3(nmol(b)), dim3(kBlock), 0, s, b.d_mols, j);
     }
+    if (m > 0)
+        hipLaunchKernelGGL(givens_kernel, dim3(nmol(b)), dim3(kBlock), 0, s, b.d_mols, m - 1);
     hipLaunchKernelGGL(update_kernel, dim3(b.n_blas), dim3(kBlock), 0, s, b.d_mols, b.d_blas);
     launch_prep(b, s, GABI_FP64, kPrepResX, 0, false);
     launch_pair(b, s, GABI_FP64, false, t);

@@ -22,6 +22,7 @@
 // summation order is the same alone or in any batch (bitwise reproducible).
 // The self term j = i is skipped exactly: only the source stages that overlap
 // the tile's own rows run the masked loop.
+#include "arnoldi.h"
 #include "gabi_internal.h"
 #include "pair_math.h"
 #include "reduce.h"
@@ -32,13 +33,33 @@ namespace gabi {
 // MODE (compile time) selects the input vector: the cycle start r/||r||
 // (stored as V_0), the Arnoldi vector w/h_{j,j-1} (stored as V_j), the
 // residual iterate, or the product input u.
+//
+// kPrepCycleJ also closes step j - 1: every workgroup reduces the partials
+// of ||w||^2 to h_{j,j-1} itself (the same bits in all of them), and the
+// molecule's first workgroup applies the Givens step, which may end the
+// cycle; the other workgroups may then still write V_j and weights that no
+// later step reads.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void prep_kernel(
     const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision,
     int j, int skip) {
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
-    if (skip && M.st->done) return;
+    double hj = 0.0;
+    if constexpr (MODE == kPrepCycleJ) {
+        // done can change during this launch (the Givens step below), so the
+        // workgroup takes one reading of it
+        __shared__ int s_done;
+        __shared__ double lds[kBlock / 64];
+        if (threadIdx.x == 0) s_done = skip && M.st->done;
+        __syncthreads();
+        if (s_done) return;
+        hj = sqrt(sum_partials(M.red + (j & 1) * kBlasBlocksMax, M.nb, lds));
+        if (e.y == 0 && threadIdx.x == 0) givens_step(M, j - 1, hj);
+        if (hj == 0.0) return;  // breakdown: the cycle has ended
+    } else {
+        if (skip && M.st->done) return;
+    }
     const int i = e.y * kBlock + threadIdx.x;
     const int n = M.n;
     if (i >= n) return;
@@ -48,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
                                             : M.u;
     double phi = src[i], psi = src[n + i];
     if constexpr (MODE == kPrepCycle0 || MODE == kPrepCycleJ) {
-        const double h = MODE == kPrepCycle0 ? M.st->rnorm : M.hn[j - 1];
+        const double h = MODE == kPrepCycle0 ? M.st->rnorm : hj;
         double *store = M.V + (size_t)(MODE == kPrepCycle0 ? 0 : j) * 2 * n;
         phi = phi / h;
         psi = psi / h;
