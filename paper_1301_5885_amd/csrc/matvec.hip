@@ -93,6 +93,36 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
                                        (float)(t * nu.z));
 }
 
+// ------------------------------------------------------------ tile order
+// A persistent grid of G workgroups drains T >= G tiles (sorted longest
+// first) in three phases.  Workgroup w takes tile w first, with no atomic:
+// G workgroups contending for one counter at the launch would start their
+// first tiles staggered.  Tiles G .. G floor(T/G) - 1 come from an atomic
+// counter, so faster workgroups take more of them.  The last partial round,
+// the remaining T mod G tiles, goes one each to workgroups 0, 1, ...: ids
+// are spread evenly over the CUs, whereas the workgroups that happen to be
+// free first are not, and a partial round taken from the queue can leave
+// some CUs with eight tiles and others with none.  A non-persistent launch
+// has one workgroup per tile.  Every thread of a workgroup calls next_tile
+// (it contains barriers, which also end the previous tile's use of LDS).
+__device__ __forceinline__ int next_tile(int persistent, int t, int ntiles, int *counter,
+                                         int *s_next) {
+    if (!persistent) return ntiles;
+    const int G = (int)gridDim.x;
+    const int queued_end = ntiles - ntiles % G;
+    if (t >= queued_end) return ntiles;  // its tile of the last partial round is done
+    if (queued_end > G) {
+        __syncthreads();
+        if (threadIdx.x == 0) *s_next = G + atomicAdd(counter, 1);
+        __syncthreads();
+        const int u = *s_next;
+        if (u < queued_end) return u;
+    } else {
+        __syncthreads();
+    }
+    return queued_end + (int)blockIdx.x;
+}
+
 // ------------------------------------------------------------------ pair
 // Per-precision views of a molecule: the FP64 product reads FP64 centroids
 // (cx, cy, cz, area) and weights (s, mx, my, mz); the FP32 one reads the
@@ -251,19 +281,11 @@ __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
     __shared__ T4 s_pos[kTile];
     __shared__ T4 s_w[kTile];
     __shared__ int s_next;
-    int t = blockIdx.x;
-    for (;;) {
-        if (persistent) {
-            __syncthreads();
-            if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
-            __syncthreads();
-            t = s_next;
-        }
-        if (t >= ntiles) break;
+    for (int t = (int)blockIdx.x; t < ntiles;
+         t = next_tile(persistent, t, ntiles, counter, &s_next)) {
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
         if (!(skip && M.st->done)) pair_tile<R, MIXED>(M, tile.y, tile.z, s_pos, s_w);
-        if (!persistent) break;
     }
 }
 
@@ -433,20 +455,12 @@ __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
     // first copies also take the column sums (2 x 4 waves x 64 per chunk)
     __shared__ T4 s_stage[4 * kTile];
     __shared__ int s_next;
-    int t = blockIdx.x;
-    for (;;) {
-        if (persistent) {
-            __syncthreads();  // also ends the previous tile's use of s_stage
-            if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
-            __syncthreads();
-            t = s_next;
-        }
-        if (t >= ntiles) break;
+    for (int t = (int)blockIdx.x; t < ntiles;
+         t = next_tile(persistent, t, ntiles, counter, &s_next)) {
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
         if (!(skip && M.st->done))
             sym_tile<MIXED>(M, tile.y, tile.z & 0xffffff, tile.z >> 24, s_stage);
-        if (!persistent) break;
     }
 }
 
