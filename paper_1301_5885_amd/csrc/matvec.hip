@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
 // every element of the chunk once in 64 steps:
 //  * I < J: each unordered pair is evaluated once; the (i, j) terms add to the
 //    lane's own row sums, the (j, i) terms to column sums that rotate through
-//    the wave with the read pattern (DPP wave_ror:1) and are back in their
+//    the wave with the read pattern (wave_rotate) and are back in their
 //    home lane after 64 steps.  The four waves' column sums of an element are
 //    added in wave order through LDS.  Row sums go to partial slot J of row
 //    i, column sums to slot I of row j.
@@ -376,6 +376,7 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
             }
         } else {
             T ctop = T(0), cbot = T(0);
+            const int from = rotate_from();
             // the next element is read one step ahead: step s reads element
             // s + 1, which for the last step is entry 0 of the chunk copy (in
             // bounds, unused).  Groups of 8 steps share one base address, so
@@ -398,8 +399,8 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
                         const PairConstF64 kc{M.kappa, M.eps, M.inv_eps};
                         sym_f64(kc, a, b, top, bot, ctop, cbot);
                     }
-                    ctop = wave_rotate(ctop);
-                    cbot = wave_rotate(cbot);
+                    ctop = wave_rotate(ctop, from);
+                    cbot = wave_rotate(cbot, from);
                     p = pn;
                     q = qn;
                 }
