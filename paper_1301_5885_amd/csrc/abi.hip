@@ -8,7 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
-#include <unordered_set>
+#include <unordered_map>
 
 #include "gabi_internal.h"
 
@@ -126,19 +126,33 @@ int validate_charges(int64_t nc, const double *px, const double *py, const doubl
 }
 
 // A charge exactly on a centroid makes a source term singular.
+// Centroid i is (c[i * cs], c[i * cs + off_y], c[i * cs + off_z]).  The
+// charges (usually far fewer than the elements) go into the hash table and
+// every centroid is looked up, so a call costs O(N + Nc) with a small table;
+// the error names the lowest-numbered charge that coincides with a centroid.
+static int charges_on_centroids(int64_t n, const double *cx, const double *cy,
+                                const double *cz, int64_t cs, int64_t nc, const double *px,
+                                const double *py, const double *pz, std::string &msg) {
+    if (n == 0 || nc == 0) return GABI_OK;
+    std::unordered_map<Key, int64_t, KeyHash> chg;
+    chg.reserve((size_t)nc * 2);
+    for (int64_t k = nc - 1; k >= 0; --k) chg[Key{px[k], py[k], pz[k]}] = k;  // lowest k wins
+    int64_t hit = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        const auto it = chg.find(Key{cx[i * cs], cy[i * cs], cz[i * cs]});
+        if (it != chg.end() && (hit < 0 || it->second < hit)) hit = it->second;
+    }
+    if (hit >= 0) {
+        msg = "charge " + std::to_string(hit) + " lies exactly on an element centroid";
+        return GABI_EINVAL;
+    }
+    return GABI_OK;
+}
+
 int check_charges_vs_centroids(int64_t n, const double *cx, const double *cy,
                                const double *cz, int64_t nc, const double *px,
                                const double *py, const double *pz, std::string &msg) {
-    if (n == 0 || nc == 0) return GABI_OK;
-    std::unordered_set<Key, KeyHash> cent;
-    cent.reserve((size_t)n * 2);
-    for (int64_t i = 0; i < n; ++i) cent.insert(Key{cx[i], cy[i], cz[i]});
-    for (int64_t k = 0; k < nc; ++k)
-        if (cent.count(Key{px[k], py[k], pz[k]})) {
-            msg = "charge " + std::to_string(k) + " lies exactly on an element centroid";
-            return GABI_EINVAL;
-        }
-    return GABI_OK;
+    return charges_on_centroids(n, cx, cy, cz, 1, nc, px, py, pz, msg);
 }
 
 int params_valid(double eps1, double eps2, double kappa) {
@@ -479,14 +493,8 @@ int gabi_set_charges(gabi_ctx *ctx, int64_t nc, const double *px,
     int rc = validate_charges(nc, px, py, pz, q, msg);
     if (rc) return fail(ctx, rc, msg);
     if (ctx->n > 0 && nc > 0) {
-        const int64_t n = ctx->n;
-        std::vector<double> cx(n), cy(n), cz(n);
-        for (int64_t i = 0; i < n; ++i) {
-            cx[i] = ctx->host_centroids[3 * i];
-            cy[i] = ctx->host_centroids[3 * i + 1];
-            cz[i] = ctx->host_centroids[3 * i + 2];
-        }
-        rc = check_charges_vs_centroids(n, cx.data(), cy.data(), cz.data(), nc, px, py, pz, msg);
+        const double *c = ctx->host_centroids.data();  // x, y, z per element
+        rc = charges_on_centroids(ctx->n, c, c + 1, c + 2, 3, nc, px, py, pz, msg);
         if (rc) return fail(ctx, rc, msg);
     }
     ctx->host_charges.resize((size_t)(4 * nc));
