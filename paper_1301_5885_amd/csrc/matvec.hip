@@ -635,7 +635,10 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
     const int pi = mixed ? 1 : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (t && t->pending[pi]) {
-        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (hipEventCreate(&e0) != hipSuccess) {
+            e0 = nullptr;
+        } else if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
             e0 = e1 = nullptr;
         } else {
             record_event(e0, s);
