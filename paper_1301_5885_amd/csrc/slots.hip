@@ -141,7 +141,7 @@ struct Carver {
 };
 
 void reaction_split(int64_t n, int64_t nc, int &kblocks, int &tps, int &splits) {
-    kblocks = (int)std::max<int64_t>(1, (nc + kBlock - 1) / kBlock);
+    kblocks = (int)std::max<int64_t>(1, (nc + 63) / 64);  // 64 charges per reaction tile
     const int64_t tiles = (n + kTile - 1) / kTile;
     int64_t want = (1024 + kblocks - 1) / kblocks;
     if (want < 1) want = 1;

@@ -53,21 +53,27 @@ void launch_rhs(const Batch &b, hipStream_t s) {
     hipLaunchKernelGGL(rhs_kernel, dim3(b.n_elem), dim3(kBlock), 0, s, b.d_mols, b.d_elem);
 }
 
-// Reaction potential: thread = charge (target), tile = (molecule, charge
-// block, split of the surface elements); partial sums [split][nc].
+// Reaction potential: tile = (molecule, block of 64 charges, split of the
+// surface elements); partial sums [split][nc].  Lane l of wave q takes charge
+// l of the block and, of every 256 staged elements, the 64 elements
+// q*64 .. q*64+63; the four waves' sums of a charge are added in wave order.
 // The source weights s_j = W_j psi_j/(4 pi), m_j = W_j phi_j nu_j/(4 pi) of the
 // evaluated vector (the solution or the product input u) are formed while the
 // sources are staged, independent of the layout the products use.
+constexpr int kRxCharges = 64;  // charges per reaction tile
+static_assert(kBlock == 4 * kRxCharges && kTile == kBlock, "four waves of 64 charges");
+
 __global__ __launch_bounds__(kBlock) void reaction_kernel(const Mol *__restrict__ mols,
                                                           const int4 *__restrict__ list,
                                                           int from_sol) {
     __shared__ double4 s_pos[kTile];
     __shared__ double4 s_w[kTile];
+    __shared__ double s_acc[kBlock];
     const int4 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
     const int n = M.n, nc = M.nc;
-    const int tid = threadIdx.x;
-    const int k = e.y * kBlock + tid;
+    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+    const int k = e.y * kRxCharges + lane;
     const double4 y = M.chg[min(k, nc - 1)];
     const PairConstF64 c{M.kappa, M.eps, M.inv_eps};
     double acc = 0.0;
@@ -87,7 +93,8 @@ __global__ __launch_bounds__(kBlock) void reaction_kernel(const Mol *__restrict_
             s_w[tid] = make_double4(c * u[n + jt + tid], t * nu.x, t * nu.y, t * nu.z);
         }
         __syncthreads();
-        for (int jj = 0; jj < cnt; ++jj) {
+        const int j1 = min(cnt, (q + 1) * 64);
+        for (int jj = q * 64; jj < j1; ++jj) {
             const double4 p = s_pos[jj];
             const double4 w = s_w[jj];
             const double dx = y.x - p.x, dy = y.y - p.y, dz = y.z - p.z;
@@ -102,7 +109,11 @@ __global__ __launch_bounds__(kBlock) void reaction_kernel(const Mol *__restrict_
             acc += __builtin_fma(__builtin_fma(c.eps, A, -1.0) * rinv * rinv * rinv, wm, k1s);
         }
     }
-    if (k < nc) M.phi_part[(size_t)e.z * nc + k] = acc;
+    s_acc[tid] = acc;
+    __syncthreads();
+    if (q == 0 && k < nc)
+        M.phi_part[(size_t)e.z * nc + k] =
+            ((s_acc[lane] + s_acc[64 + lane]) + s_acc[128 + lane]) + s_acc[192 + lane];
 }
 
 // one workgroup per molecule: phi_reac = sum over splits, E = 1/2 sum q phi
