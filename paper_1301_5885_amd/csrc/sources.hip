@@ -16,14 +16,19 @@
 
 namespace gabi {
 
+// Right-hand side: workgroup = 64 elements of a 256-element block (the block
+// list entry blockIdx.x / 4, quarter blockIdx.x % 4); lane l of wave q takes
+// element l and the charges q, q + 4, ... of every 256 staged; the four
+// waves' sums of an element are added in wave order.
 __global__ __launch_bounds__(kBlock) void rhs_kernel(const Mol *__restrict__ mols,
                                                      const int2 *__restrict__ list) {
     __shared__ double4 s_c[kTile];
-    const int2 e = list[blockIdx.x];
+    __shared__ double s_acc[2][kBlock];
+    const int2 e = list[blockIdx.x / 4];
     const Mol &M = mols[e.x];
     const int n = M.n, nc = M.nc;
-    const int tid = threadIdx.x;
-    const int i = e.y * kBlock + tid;
+    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+    const int i = e.y * kBlock + (int)(blockIdx.x % 4) * 64 + lane;
     const int ic = min(i, n - 1);
     const double4 x = M.pos[ic];
     const double4 nu = M.nrm[ic];
@@ -33,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void rhs_kernel(const Mol *__restrict__ mol
         __syncthreads();
         if (tid < cnt) s_c[tid] = M.chg[kt + tid];
         __syncthreads();
-        for (int kk = 0; kk < cnt; ++kk) {
+        for (int kk = q; kk < cnt; kk += 4) {
             const double4 c = s_c[kk];
             const double dx = x.x - c.x, dy = x.y - c.y, dz = x.z - c.z;
             const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
@@ -43,14 +48,21 @@ __global__ __launch_bounds__(kBlock) void rhs_kernel(const Mol *__restrict__ mol
             s2 = __builtin_fma(c.w * ux, rinv * rinv * rinv, s2);
         }
     }
-    if (i < n) {
-        M.rhs_dst[i] = s1 * M.rhs_scale;
-        M.rhs_dst[n + i] = -s2 * M.rhs_scale;
+    s_acc[0][tid] = s1;
+    s_acc[1][tid] = s2;
+    __syncthreads();
+    if (q == 0 && i < n) {
+        const double t1 = ((s_acc[0][lane] + s_acc[0][64 + lane]) + s_acc[0][128 + lane]) +
+                          s_acc[0][192 + lane];
+        const double t2 = ((s_acc[1][lane] + s_acc[1][64 + lane]) + s_acc[1][128 + lane]) +
+                          s_acc[1][192 + lane];
+        M.rhs_dst[i] = t1 * M.rhs_scale;
+        M.rhs_dst[n + i] = -t2 * M.rhs_scale;
     }
 }
 
 void launch_rhs(const Batch &b, hipStream_t s) {
-    hipLaunchKernelGGL(rhs_kernel, dim3(b.n_elem), dim3(kBlock), 0, s, b.d_mols, b.d_elem);
+    hipLaunchKernelGGL(rhs_kernel, dim3(4 * b.n_elem), dim3(kBlock), 0, s, b.d_mols, b.d_elem);
 }
 
 // Reaction potential: tile = (molecule, block of 64 charges, split of the
