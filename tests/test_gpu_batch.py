@@ -158,6 +158,18 @@ def test_graph_replay_matches_eager():
             a, _ = ctx.solve(tol=1e-10, use_graph=0, mode=mode)
             b, _ = ctx.solve(tol=1e-10, use_graph=1, mode=mode)
             assert np.array_equal(a, b)
+        # a round captured with timing events around its products: same bits,
+        # and every product launch is timed
+        ctx.kernel_time(gabi.FP64, reset=True)
+        ctx.set_kernel_timing(True)
+        for _ in range(2):
+            u_timed, i_timed = ctx.solve(tol=1e-10, use_graph=1)
+            assert np.array_equal(u_timed, u_eager)
+        ctx.set_kernel_timing(False)
+        ms, count = ctx.kernel_time(gabi.FP64, reset=True)
+        assert ms > 0 and count >= 2 * i_timed["matvecs_fp64"] - 2
+        u_after, _ = ctx.solve(tol=1e-10, use_graph=1)   # captured again without events
+        assert np.array_equal(u_after, u_eager)
 
 
 def test_batch_handles_failures_per_problem():
