@@ -13,8 +13,9 @@
 //           (coalesced loads, broadcast reads), and writes its two row sums
 //           per target to the molecule's partial buffer.  Tiles of every
 //           molecule in the batch are listed longest first; the persistent
-//           form runs a fixed grid whose workgroups take tiles from an
-//           atomic counter until the list is exhausted, the flat form
+//           form runs a fixed grid that drains the list in the order of
+//           next_tile (first round by workgroup id, then an atomic counter,
+//           the last partial round by workgroup id again), the flat form
 //           launches one workgroup per tile;
 //   finish  O(N S): adds the split partials in split order, applies the
 //           diagonal, and (inside GMRES) emits the first MGS dot partial.
