@@ -1,6 +1,7 @@
 // Per-molecule device memory (slots), product decomposition and the tuning
 // table it is read from, and batches (block lists over many molecules).
 #include <algorithm>
+#include <map>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -361,19 +362,55 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     // group by kernel variant (split with two rows per thread, split with one,
     // symmetric), longest tiles first within a group; ties keep molecule and
     // tile order
+    // (a stable counting sort over the few distinct (group, cost) keys: a
+    // comparison sort of a large batch's tiles took milliseconds per rebuild)
     auto group = [&](std::vector<int4> &t, bool mixed, int *counts) {
-        auto G = [&](const int4 &a) {
-            const Mol &M = b.slots[a.x]->mol;
-            if (mixed ? M.sym32 : M.sym64) return 2;
-            return (mixed ? M.R32 : M.R64) == 2 ? 0 : 1;
+        std::vector<int> gm((size_t)nm);
+        for (int k = 0; k < nm; ++k) {
+            const Mol &M = b.slots[k]->mol;
+            gm[k] = (mixed ? M.sym32 : M.sym64) ? 2 : (mixed ? M.R32 : M.R64) == 2 ? 0 : 1;
+        }
+        // ascending key = group ascending, then cost descending
+        auto key = [&](const int4 &a) {
+            return ((int64_t)gm[a.x] << 32) | (int64_t)(0x7fffffff - a.w);
         };
-        std::stable_sort(t.begin(), t.end(), [&](const int4 &a, const int4 &c) {
-            const int ga = G(a), gc = G(c);
-            if (ga != gc) return ga < gc;
-            return a.w > c.w;
-        });
+        // consecutive tiles mostly share a key, so the map is consulted only
+        // when the key changes
+        std::map<int64_t, size_t> start;
+        {
+            int64_t last = -1;
+            size_t *cnt = nullptr;
+            for (const int4 &a : t) {
+                const int64_t kk = key(a);
+                if (kk != last) {
+                    cnt = &start[kk];
+                    last = kk;
+                }
+                ++*cnt;
+            }
+        }
+        size_t off = 0;
+        for (auto &kv : start) {
+            const size_t c = kv.second;
+            kv.second = off;
+            off += c;
+        }
+        std::vector<int4> out(t.size());
+        {
+            int64_t last = -1;
+            size_t *pos = nullptr;
+            for (const int4 &a : t) {
+                const int64_t kk = key(a);
+                if (kk != last) {
+                    pos = &start[kk];
+                    last = kk;
+                }
+                out[(*pos)++] = a;
+            }
+        }
+        t.swap(out);
         counts[0] = counts[1] = counts[2] = 0;
-        for (const int4 &a : t) counts[G(a)]++;
+        for (const int4 &a : t) counts[gm[a.x]]++;
     };
     int c64[3], c32[3];
     group(t64, false, c64);
