@@ -88,11 +88,14 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("kappa", [KAPPA, 0.0, 0.3])
+# every case at the workloads' kappa, at kappa = 0 (E = A = 1, B = 3: K1 = 0) and at
+# a larger kappa; the full-size case only at the workload's kappa
+MATVEC_CASES = [(name, kappa) for kappa in (KAPPA, 0.0, 0.3) for name in CASES
+                if name != "kirkwood_20480" or kappa == KAPPA]
+
+
+@pytest.mark.parametrize("name,kappa", MATVEC_CASES)
 def test_matvec_fp64_matches_oracle(ctx, name, kappa):
-    if name == "kirkwood_20480" and kappa != KAPPA:
-        pytest.skip("full-size case checked at the workload's kappa")
     V, F, pos, q = CASES[name]()
     log(f"[matvec fp64] {name} N={len(F)} kappa={kappa}")
     el = load(ctx, V, F, pos, q, kappa=kappa)
@@ -103,11 +106,8 @@ def test_matvec_fp64_matches_oracle(ctx, name, kappa):
     assert rel(y, y_ref) <= 1e-10 and relmax(y, y_ref) <= 1e-10, (rel(y, y_ref), relmax(y, y_ref))
 
 
-@pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("kappa", [KAPPA, 0.0, 0.3])
+@pytest.mark.parametrize("name,kappa", MATVEC_CASES)
 def test_matvec_fp32_pair_matches_oracle(ctx, name, kappa):
-    if name == "kirkwood_20480" and kappa != KAPPA:
-        pytest.skip("full-size case checked at the workload's kappa")
     V, F, pos, q = CASES[name]()
     log(f"[matvec fp32-pair] {name} N={len(F)} kappa={kappa}")
     el = load(ctx, V, F, pos, q, kappa=kappa)
