@@ -16,6 +16,11 @@ __device__ __forceinline__ double sum_partials(const double *red, int nb, double
     return block_sum(v, lds);
 }
 
+// The slot of M.red that holds the partials of the projected ||w||^2.
+__device__ __forceinline__ double *norm_slot(const Mol &M) {
+    return M.red + (size_t)2 * M.m * kBlasBlocksMax;
+}
+
 // Step j of the cycle closes with h_{j+1,j} = hn = ||w||: the earlier
 // rotations are applied to column j of H, a new rotation zeroes h_{j+1,j},
 // the residual estimate |g_{j+1}| is updated, and the cycle stops on the

@@ -116,8 +116,11 @@ struct Mol {
     double *b, *x, *r, *w, *bo, *xo, *sol;
     // role pointers set by the solve mode (see krylov.hip)
     double *rhs_dst, *cyc_src, *upd_dst, *res_x, *res_b, *res_out;
-    // Krylov
-    double *V, *H, *cs, *sn, *g, *hn, *red;
+    // Krylov.  red: partial-sum slots of kBlasBlocksMax doubles (slot 0
+    // <w, v_0> or a residual norm, slots 1..2j a step's dot products, slot 2m
+    // the projected ||w||^2); G: the cycle's Gram entries <v_k, v_i>, k < i,
+    // packed by rows (row i at i(i-1)/2)
+    double *V, *H, *cs, *sn, *g, *hn, *red, *G;
     KrylovStatus *st;
     // reaction potential at the charges
     double *phi, *phi_part;

@@ -6,12 +6,11 @@
 // Arnoldi with modified Gram-Schmidt: for step j, w = A v_j, then for
 // i = 0..j in order h_ij = <w, v_i>, w <- w - h_ij v_i; h_{j+1,j} = ||w||;
 // Givens rotations reduce H to triangular form and carry the residual
-// estimate |g_{j+1}|.  Every MGS substep is one launch over all molecules:
-// each workgroup adds its molecule's fixed-order dot partials (all
-// workgroups of a molecule agree bitwise), applies the previous update to
-// its slice of w and emits its partial of the next dot product.  A per
-// molecule device flag ends its cycle early (estimate below tol, breakdown,
-// iteration cap); the remaining launches skip that molecule.
+// estimate |g_{j+1}|.  The MGS coefficients are formed from one reduction
+// per step (gram_kernel, project_kernel below): each workgroup adds its
+// molecule's fixed-order dot partials (all workgroups of a molecule agree
+// bitwise).  A per molecule device flag ends its cycle early (estimate below
+// tol, breakdown, iteration cap); the remaining launches skip that molecule.
 //
 // A round is: one cycle of m Arnoldi steps, x += V y, the explicit FP64
 // residual, and the start of the next cycle.  For the FP64 solver the cycle
@@ -116,61 +115,92 @@ __global__ __launch_bounds__(kBlock) void start_kernel(const Mol *__restrict__ m
     st->done = (conv || st->iters >= st->maxit) ? 1 : 0;
 }
 
-// MGS substep i of step j (i = j + 1: the closing norm).  h = <w, v_{i-1}>
-// from the partials, w -= h v_{i-1}, partials of <w, v_i> (or of <w, w>).
-__global__ __launch_bounds__(kBlock) void mgs_kernel(const Mol *__restrict__ mols,
-                                                     const int2 *__restrict__ list,
-                                                     int i, int j) {
+// Modified Gram-Schmidt in one reduction per step.  MGS takes h_i as the dot
+// of v_i with w after the first i subtractions, so h_i = c_i - sum_{k<i}
+// L_ik h_k with c_i = <w, v_i> and the Gram entries L_ik = <v_k, v_i>: every
+// coefficient follows from dot products of the unmodified vectors, which
+// one launch computes, instead of j + 1 dependent launches.
+//
+// gram_kernel: partials of the dot products of step j beyond <w, v_0> (the
+// product's finish emits that one into slot 0).  Grid (blas blocks, 2j):
+// slot d = 1..j gets <w, v_d>, slot j + 1 + k (k < j) gets <v_k, v_j>.
+__global__ __launch_bounds__(kBlock) void gram_kernel(const Mol *__restrict__ mols,
+                                                      const int2 *__restrict__ list, int j) {
+    __shared__ double lds[kBlock / 64];
+    const int2 e = list[blockIdx.x];
+    const Mol &M = mols[e.x];
+    if (M.st->done) return;
+    const int n = M.n, nb = M.nb;
+    const size_t len = 2 * (size_t)n;
+    const int d = (int)blockIdx.y + 1;
+    const double *a = d <= j ? M.w : M.V + (size_t)(d - j - 1) * len;
+    const double *c = M.V + (size_t)(d <= j ? d : j) * len;
+    double s = 0.0;
+    for (int t = e.y * kBlock + threadIdx.x; t < n; t += nb * kBlock)
+        s = __builtin_fma(a[t], c[t], __builtin_fma(a[n + t], c[n + t], s));
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) M.red[(size_t)d * kBlasBlocksMax + e.y] = s;
+}
+
+// project_kernel: every workgroup adds the 2j + 1 dot products (wave q takes
+// slots q, q + 4, ... in lane order, so all workgroups agree bitwise), solves
+// for h_0..h_j, sets w <- w - sum_i h_i v_i on its slice (i ascending, as MGS
+// subtracts) and emits its partial of ||w||^2.  The molecule's first
+// workgroup stores column j of H and Gram row j for the later steps.
+__global__ __launch_bounds__(kBlock) void project_kernel(const Mol *__restrict__ mols,
+                                                         const int2 *__restrict__ list, int j) {
+    __shared__ double s_dot[2 * kMaxRestart];
+    __shared__ double s_L[kMaxRestart * (kMaxRestart - 1) / 2];
+    __shared__ double s_h[kMaxRestart];
     __shared__ double lds[kBlock / 64];
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
     if (M.st->done) return;
     const int n = M.n, nb = M.nb, m = M.m;
     const size_t len = 2 * (size_t)n;
-    const double *red_in = M.red + ((i - 1) & 1) * kBlasBlocksMax;
-    double *red_out = M.red + (i & 1) * kBlasBlocksMax;
-    const double *vp = M.V + (size_t)(i - 1) * len;
-    const double *vn = i <= j ? M.V + (size_t)i * len : nullptr;
-    double *w = M.w;
-    // the first element's operands are loaded before the partials are
-    // reduced, so the memory latencies overlap
-    const int t0 = e.y * kBlock + threadIdx.x;
-    double p0 = 0.0, p1 = 0.0, w0 = 0.0, w1 = 0.0, n0 = 0.0, n1 = 0.0;
-    if (t0 < n) {
-        p0 = vp[t0];
-        p1 = vp[n + t0];
-        w0 = w[t0];
-        w1 = w[n + t0];
-        if (vn) {
-            n0 = vn[t0];
-            n1 = vn[n + t0];
+    const int nl = j * (j - 1) / 2;  // Gram rows 1..j-1
+    for (int t = threadIdx.x; t < nl; t += kBlock) s_L[t] = M.G[t];
+    const int lane = threadIdx.x & 63;
+    for (int d0 = 0; d0 <= 2 * j; d0 += kBlock / 64) {  // same trip count in every wave
+        const int d = d0 + (threadIdx.x >> 6);
+        double v = 0.0;
+        if (d <= 2 * j) {
+            const double *p = M.red + (size_t)d * kBlasBlocksMax;
+            for (int t = lane; t < nb; t += 64) v += p[t];
         }
+        v = wave_total_lane63(v);
+        if (lane == 63 && d <= 2 * j) s_dot[d] = v;
     }
-    const double h = sum_partials(red_in, nb, lds);
-    if (e.y == 0 && threadIdx.x == 0) M.H[(i - 1) * m + j] = h;
-    double s = 0.0;
-    for (int t = t0; t < n; t += nb * kBlock) {
-        if (t != t0) {
-            p0 = vp[t];
-            p1 = vp[n + t];
-            w0 = w[t];
-            w1 = w[n + t];
-            if (vn) {
-                n0 = vn[t];
-                n1 = vn[n + t];
-            }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const bool first = e.y == 0;
+        for (int i = 0; i <= j; ++i) {
+            const double *Li = i < j ? s_L + i * (i - 1) / 2 : s_dot + j + 1;
+            double c = s_dot[i];
+            for (int k = 0; k < i; ++k) c = __builtin_fma(-Li[k], s_h[k], c);
+            s_h[i] = c;
+            if (first) M.H[i * m + j] = c;
         }
-        const double wt = __builtin_fma(-h, p0, w0);
-        const double wb = __builtin_fma(-h, p1, w1);
+        if (first)
+            for (int k = 0; k < j; ++k) M.G[nl + k] = s_dot[j + 1 + k];
+    }
+    __syncthreads();
+    double *w = M.w;
+    double s = 0.0;
+    for (int t = e.y * kBlock + threadIdx.x; t < n; t += nb * kBlock) {
+        double wt = w[t], wb = w[n + t];
+        const double *v = M.V + t;
+#pragma unroll 4
+        for (int i = 0; i <= j; ++i) {
+            wt = __builtin_fma(-s_h[i], v[(size_t)i * len], wt);
+            wb = __builtin_fma(-s_h[i], v[(size_t)i * len + n], wb);
+        }
         w[t] = wt;
         w[n + t] = wb;
-        if (vn)
-            s = __builtin_fma(wt, n0, __builtin_fma(wb, n1, s));
-        else
-            s = __builtin_fma(wt, wt, __builtin_fma(wb, wb, s));
+        s = __builtin_fma(wt, wt, __builtin_fma(wb, wb, s));
     }
     s = block_sum(s, lds);
-    if (threadIdx.x == 0) red_out[e.y] = s;
+    if (threadIdx.x == 0) norm_slot(M)[e.y] = s;
 }
 
 // one workgroup per molecule: the Givens step that closes step j (the last
@@ -179,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void givens_kernel(const Mol *__restrict__ 
     __shared__ double lds[kBlock / 64];
     const Mol &M = mols[blockIdx.x];
     if (M.st->done) return;
-    const double hn = sqrt(sum_partials(M.red + ((j + 1) & 1) * kBlasBlocksMax, M.nb, lds));
+    const double hn = sqrt(sum_partials(norm_slot(M), M.nb, lds));
     if (threadIdx.x == 0) givens_step(M, j, hn);
 }
 
@@ -256,9 +286,11 @@ void enqueue_round(Batch &b, hipStream_t s, const Timer *t) {
         launch_prep(b, s, prec, j == 0 ? kPrepCycle0 : kPrepCycleJ, j, true);
         launch_pair(b, s, prec, true, t);
         launch_finish(b, s, prec, kFinishDot, j, true);
-        for (int i = 1; i <= j + 1; ++i)
-            hipLaunchKernelGGL(mgs_kernel, dim3(b.n_blas), dim3(kBlock), 0, s, b.d_mols,
-                               b.d_blas, i, j);
+        if (j > 0)
+            hipLaunchKernelGGL(gram_kernel, dim3(b.n_blas, 2 * j), dim3(kBlock), 0, s,
+                               b.d_mols, b.d_blas, j);
+        hipLaunchKernelGGL(project_kernel, dim3(b.n_blas), dim3(kBlock), 0, s, b.d_mols,
+                           b.d_blas, j);
     }
     if (m > 0)
         hipLaunchKernelGGL(givens_kernel, dim3(nmol(b)), dim3(kBlock), 0, s, b.d_mols, m - 1);

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
         if (threadIdx.x == 0) s_done = skip && M.st->done;
         __syncthreads();
         if (s_done) return;
-        hj = sqrt(sum_partials(M.red + (j & 1) * kBlasBlocksMax, M.nb, lds));
+        hj = sqrt(sum_partials(norm_slot(M), M.nb, lds));
         if (e.y == 0 && threadIdx.x == 0) givens_step(M, j - 1, hj);
         if (hj == 0.0) return;  // breakdown: the cycle has ended
     } else {

@@ -188,7 +188,8 @@ int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
     t.sn = c.take<double>(m);
     t.g = c.take<double>(m + 1);
     t.hn = c.take<double>(m);
-    t.red = c.take<double>(2 * kBlasBlocksMax);
+    t.red = c.take<double>((int64_t)(2 * m + 1) * kBlasBlocksMax);
+    t.G = c.take<double>(std::max<int64_t>(1, (int64_t)m * (m - 1) / 2));
     t.st = c.take<KrylovStatus>(1);
     t.phi = c.take<double>(nc);
     t.phi_part = c.take<double>(nc * sp);
