@@ -190,6 +190,26 @@ def test_solve_fp64_matches_oracle(ctx, name):
     assert abs(E / oracle.energy(el, u, pos, q) - 1) <= 1e-12
 
 
+@pytest.mark.parametrize("restart", [5, 40, 64])
+def test_solve_fp64_cycle_lengths_match_oracle(ctx, restart):
+    """Short and long Arnoldi cycles (64 is the largest restart accepted): the
+    device forms the MGS coefficients of a step from one reduction, the oracle
+    runs plain MGS; at the same restart and tol both take the same number of
+    steps to within one and land on the same solution."""
+    V, F, pos, q = CASES["star_4500_ragged"]()
+    log(f"[solve fp64 restart {restart}]")
+    el = load(ctx, V, F, pos, q)
+    b = oracle.rhs(el, pos, q)
+    u_ref, info_ref = oracle.gmres(el, b, EPS1, EPS2, KAPPA, restart=restart, tol=1e-10,
+                                   maxit=400)
+    u, info = ctx.solve(tol=1e-10, restart=restart, maxit=400)
+    log(f"    gpu {info} oracle {info_ref}")
+    assert info_ref["rel_residual"] <= 1e-10
+    assert info["converged"] and info["rel_residual"] <= 1e-10
+    assert abs(info["iterations"] - info_ref["iterations"]) <= 1
+    assert rel(u, u_ref) <= 1e-8
+
+
 @pytest.mark.parametrize("name", SOLVE_CASES + ["kirkwood_20480"])
 def test_solve_mixed_ir_energy_gate(ctx, name):
     V, F, pos, q = CASES[name]()
