@@ -319,3 +319,42 @@ def test_rotation_invariance():
     ur, Er, _ = oracle.solve(el_r, p.pos @ Rm.T, p.q, tol=1e-12)
     assert np.allclose(u, ur, rtol=0, atol=1e-9 * np.abs(u).max())
     assert Er == pytest.approx(E, rel=1e-9)
+
+
+# ------------------------------------------------- sampled rows of A u
+@pytest.mark.parametrize("nu", [4, 8])
+@pytest.mark.parametrize("kappa", [0.0, KAPPA])
+def test_matvec_rows_equals_product(nu, kappa):
+    """oracle.matvec_rows over all 2N rows, in shuffled order, is bitwise
+    the whole product oracle.matvec (both sum over j in index order; the
+    product is pinned by the sphere integrals, LU and the Born ion), so the
+    sampled-row checker of the largest products carries the same pins."""
+    V, F = icosphere(nu, 3.0)
+    el = oracle.mesh_elements(V, F)
+    n = el.n
+    rng = np.random.default_rng(nu)
+    u = rng.normal(size=2 * n)
+    y = oracle.matvec(el, u, EPS1, EPS2, kappa)
+    rows = rng.permutation(2 * n)
+    yr = oracle.matvec_rows(el, u, rows, EPS1, EPS2, kappa)
+    assert np.array_equal(yr, y[rows])
+
+
+def test_matvec_rows_born_residual():
+    """The Born ion's exact surface values satisfy every sampled row of the
+    discrete equations A u = b to O(h): the error falls as the mesh is
+    refined (Section 2.2 collocation; independent of the product routine)."""
+    a, q = 2.0, 1.0
+    phi, psi = born_surface(a, q, EPS1, EPS2, KAPPA)
+    errs = []
+    for nu in (4, 8, 16):
+        V, F = icosphere(nu, a)
+        el = oracle.mesh_elements(V, F)
+        n = el.n
+        u = np.r_[np.full(n, phi), np.full(n, psi)]
+        rows = np.r_[np.arange(0, n, max(1, n // 16)), n + np.arange(0, n, max(1, n // 16))]
+        y = oracle.matvec_rows(el, u, rows, EPS1, EPS2, KAPPA)
+        b = oracle.rhs(el, np.zeros((1, 3)), [q], EPS1)[rows]
+        errs.append(np.max(np.abs(y - b) / np.abs(b)))
+    assert errs[0] < 0.1
+    assert errs[1] < errs[0] and errs[2] < errs[1]

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from closed_forms import born_energy, sphere_kernel_integrals
+from closed_forms import born_energy, born_surface, sphere_kernel_integrals
 from paper_1301_5885_amd.synth import icosphere
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
@@ -44,6 +44,17 @@ MUTANTS = {
                     "H[(i + 1) * m + j] = sn[i] * a + cs[i] * c;"),
     "mgs_skips_last": ("for (int64_t i = 0; i <= j; ++i) {\n                double *vi",
                        "for (int64_t i = 0; i < j; ++i) {\n                double *vi"),
+    # the sampled-row product (sole checker of the largest products)
+    "rows_diagonal_swapped": (
+        "out[r] = bottom ? 0.5 * (1.0 + 1.0 / eps) * u[n + i] - s\n"
+        "                        : 0.5 * (1.0 + eps) * u[i] - s;",
+        "out[r] = bottom ? 0.5 * (1.0 + eps) * u[n + i] - s\n"
+        "                        : 0.5 * (1.0 + 1.0 / eps) * u[i] - s;"),
+    "rows_bottom_transposed": (
+        "s += area[j] * (K[2] * u[n + j] + K[3] * u[j]);",
+        "s += area[j] * (K[2] * u[j] + K[3] * u[n + j]);"),
+    "rows_index_shift": ("int64_t i = row < n ? row : row - n;",
+                         "int64_t i = row < n ? row : row - n + 1;"),
 }
 
 
@@ -100,6 +111,23 @@ def _pins():
     if abs(K[0] - Ks[0]) > 1e-14 * abs(K[0]) or abs(K[3] - Ks[3]) > 1e-12 * abs(K[3]) \
             or abs(K[1] - k2) > 1e-12 * abs(k2):
         failed.append("pair_identities")
+    # sampled rows of the product: the Born surface values (the continuous
+    # solution) satisfy the discrete equations to O(h) at every row, and the
+    # rows of the upper and lower halves differ in diagonal and kernels
+    phi_b, psi_b = born_surface(a, 1.0, 1.0, eps, kap)
+    ub = np.r_[np.full(n, phi_b), np.full(n, psi_b)]
+    rows = np.array([0, 7, n - 1, n, n + 7, 2 * n - 1])
+    yr = oracle.matvec_rows(el, ub, rows, 1.0, eps, kap)
+    bb0 = oracle.rhs(el, np.zeros((1, 3)), [1.0])
+    scale = np.abs(bb0[rows])
+    if np.any(np.abs(yr - bb0[rows]) > 0.1 * scale):
+        failed.append("rows_born_residual")
+    # the sampled rows against the whole product (itself pinned above) on a
+    # random vector, all 2N rows
+    ur = np.random.default_rng(3).normal(size=2 * n)
+    if not np.array_equal(oracle.matvec_rows(el, ur, np.arange(2 * n), 1.0, eps, kap),
+                          oracle.matvec(el, ur, 1.0, eps, kap)):
+        failed.append("rows_vs_product")
     return failed
 
 
