@@ -152,8 +152,11 @@ int gabi_set_surface(gabi_ctx *ctx, int64_t n, const double *cx,
 int gabi_set_surface_mesh(gabi_ctx *ctx, int64_t nv, const double *xyz,
                           int64_t nf, const int32_t *tri);
 
-/* Set the point charges: positions (px,py,pz) in Angstrom and charges q in
- * units of e, host arrays of length nc >= 0 (nc = 0 gives b = 0, u = 0 and
+/* Set the point charges of the solute, the sources of the interior
+ * equation (Section 1, eq. (eq1): the sum of point charges q_k at y_k on the
+ * right-hand side; they enter the source terms S1, S2 of eq. (Eq_Ss) and the
+ * energy sum of eq. (solvation_energy)): positions (px,py,pz) in Angstrom
+ * and charges q in units of e, host arrays of length nc >= 0 (nc = 0 gives b = 0, u = 0 and
  * E = 0).  Non-finite values: GABI_EINVAL.  A charge exactly on an element
  * centroid is rejected with GABI_EINVAL when both surface and charges are
  * set.                                                                      */
@@ -259,7 +262,8 @@ int gabi_tune_get(int precision, int bucket, int *scheme, int *rows_per_thread,
  * All arrays are host memory read during the call that takes the problem.
  * u_out: optional host buffer of 2N doubles that receives the solution; the
  * caller keeps it valid until the result has been returned.  tag: any
- * caller value, copied into the result.                                    */
+ * caller value, copied into the result (tags need not be unique; the
+ * result's ticket identifies the request).                                 */
 typedef struct {
     int64_t n;
     const double *cx, *cy, *cz, *nx, *ny, *nz, *area;
@@ -279,6 +283,9 @@ typedef struct {
     double t_admit;        /* admitted to the device                       */
     double t_done;         /* result ready                                 */
     int64_t device_bytes;  /* device memory the solve held                 */
+    int64_t ticket;        /* the server's sequence number of the request
+                              (gabi_server_submit); the problem index in
+                              gabi_batch_solve                              */
 } gabi_result;
 
 /* Device bytes one solve of n elements and nc charges holds with GMRES(m)

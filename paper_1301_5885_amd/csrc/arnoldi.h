@@ -8,6 +8,17 @@
 
 namespace gabi {
 
+// The cycle-end flag of a molecule.  Within one launch of the prep kernel
+// the molecule's first workgroup may set it (the Givens step) while the
+// other workgroups read it, so every access is a relaxed atomic at agent
+// scope; launches on one stream are ordered, so no stronger order is needed.
+__device__ __forceinline__ int load_done(const KrylovStatus *st) {
+    return __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_done(KrylovStatus *st, int v) {
+    __hip_atomic_store(&st->done, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Sum of a molecule's nb per-workgroup partials in block order (every
 // workgroup that calls it gets the same bits).  Contains __syncthreads().
 __device__ __forceinline__ double sum_partials(const double *red, int nb, double *lds) {
@@ -48,7 +59,7 @@ __device__ inline void givens_step(const Mol &M, int j, double hn) {
     st->k = j + 1;
     st->gabs = fabs(g[j + 1]);
     if (fabs(g[j + 1]) / st->beta <= st->tol || st->iters >= st->maxit || hn == 0.0)
-        st->done = 1;
+        store_done(st, 1);
 }
 
 }  // namespace gabi

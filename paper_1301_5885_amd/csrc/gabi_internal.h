@@ -139,6 +139,7 @@ struct Slot {
     int64_t arena_off = 0;
     // solve bookkeeping
     int64_t tag = 0;
+    int64_t ticket = 0;       // request sequence number (server) or index (batch)
     int32_t rounds = 0;
     int64_t products64 = 0, products32 = 0;
     int32_t last_iters = 0;

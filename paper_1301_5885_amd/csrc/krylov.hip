@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Mol *__restrict__ mo
         st->maxit = M.maxit;
         st->iters = 0;
         st->k = 0;
-        st->done = 0;
+        store_done(st, 0);
         st->converged = 0;
         st->rnorm = st->beta0;
         st->gabs = st->beta0;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void start_kernel(const Mol *__restrict__ m
     }
     for (int i = 0; i <= M.m; ++i) M.g[i] = 0.0;
     M.g[0] = rn;
-    st->done = (conv || st->iters >= st->maxit) ? 1 : 0;
+    store_done(st, (conv || st->iters >= st->maxit) ? 1 : 0);
 }
 
 // Modified Gram-Schmidt in one reduction per step.  MGS takes h_i as the dot
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(const Mol *__restrict__ mo
     __shared__ double lds[kBlock / 64];
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
-    if (M.st->done) return;
+    if (load_done(M.st)) return;
     const int n = M.n, nb = M.nb;
     const size_t len = 2 * (size_t)n;
     const int d = (int)blockIdx.y + 1;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(const Mol *__restrict__
     __shared__ double lds[kBlock / 64];
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
-    if (M.st->done) return;
+    if (load_done(M.st)) return;
     const int n = M.n, nb = M.nb, m = M.m;
     const size_t len = 2 * (size_t)n;
     const int nl = j * (j - 1) / 2;  // Gram rows 1..j-1
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(const Mol *__restrict__
 __global__ __launch_bounds__(kBlock) void givens_kernel(const Mol *__restrict__ mols, int j) {
     __shared__ double lds[kBlock / 64];
     const Mol &M = mols[blockIdx.x];
-    if (M.st->done) return;
+    if (load_done(M.st)) return;
     const double hn = sqrt(sum_partials(norm_slot(M), M.nb, lds));
     if (threadIdx.x == 0) givens_step(M, j, hn);
 }

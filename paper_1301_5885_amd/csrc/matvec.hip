@@ -52,14 +52,14 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
         // workgroup takes one reading of it
         __shared__ int s_done;
         __shared__ double lds[kBlock / 64];
-        if (threadIdx.x == 0) s_done = skip && M.st->done;
+        if (threadIdx.x == 0) s_done = skip && load_done(M.st);
         __syncthreads();
         if (s_done) return;
         hj = sqrt(sum_partials(norm_slot(M), M.nb, lds));
         if (e.y == 0 && threadIdx.x == 0) givens_step(M, j - 1, hj);
         if (hj == 0.0) return;  // breakdown: the cycle has ended
     } else {
-        if (skip && M.st->done) return;
+        if (skip && load_done(M.st)) return;
     }
     const int i = e.y * kBlock + threadIdx.x;
     const int n = M.n;
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
          t = next_tile(persistent, t, ntiles, counter, &s_next)) {
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
-        if (!(skip && M.st->done)) pair_tile<R, MIXED>(M, tile.y, tile.z, s_pos, s_w);
+        if (!(skip && load_done(M.st))) pair_tile<R, MIXED>(M, tile.y, tile.z, s_pos, s_w);
     }
 }
 
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
          t = next_tile(persistent, t, ntiles, counter, &s_next)) {
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
-        if (!(skip && M.st->done))
+        if (!(skip && load_done(M.st)))
             sym_tile<MIXED>(M, tile.y, tile.z & 0xffffff, tile.z >> 24, s_stage);
     }
 }
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
     if (blockIdx.x == 0 && threadIdx.x < kPairVariants) counters[threadIdx.x] = 0;
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
-    if (skip && M.st->done) return;
+    if (skip && load_done(M.st)) return;
     const int n = M.n, nb = M.nb;
     const int q = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
     const int splits = precision == GABI_FP64 ? M.sp64 : M.sp32;

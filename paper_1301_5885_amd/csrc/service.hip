@@ -45,6 +45,7 @@ struct Staged {
     double eps1 = 1, eps2 = 80, kappa = 0;
     double *u_out = nullptr;
     int64_t tag = 0;
+    int64_t ticket = 0;
     int64_t bytes = 0;
     double t_submit = 0;
 };
@@ -324,6 +325,7 @@ gabi_result make_result(const Slot &s) {
     const KrylovStatus &st = s.host_st;
     gabi_result r{};
     r.tag = s.tag;
+    r.ticket = s.ticket;
     r.status = st.converged ? GABI_OK : GABI_NOT_CONVERGED;
     r.energy = st.energy;
     r.info.iterations = st.iters;
@@ -397,6 +399,7 @@ void gabi_server::run() {
         for (auto &f : fresh) {
             auto s = std::make_unique<Slot>();
             s->tag = f.first->tag;
+            s->ticket = f.first->ticket;
             s->u_out = f.first->u_out;
             s->t_submit = f.first->t_submit;
             s->t_admit = clock();
@@ -409,6 +412,7 @@ void gabi_server::run() {
                 err = e;
                 gabi_result r{};
                 r.tag = s->tag;
+                r.ticket = s->ticket;
                 r.status = rc;
                 r.t_submit = s->t_submit;
                 r.t_admit = s->t_admit;
@@ -505,6 +509,7 @@ int gabi_batch_solve(int device, int64_t nprob, const gabi_problem *probs,
     for (int64_t k = 0; k < nprob; ++k) {
         results[k] = gabi_result{};
         results[k].tag = probs[k].tag;
+        results[k].ticket = k;
         int rc = stage_problem(probs[k], o.restart, staged[k], err);
         if (rc) {
             results[k].status = rc;
@@ -525,6 +530,7 @@ int gabi_batch_solve(int device, int64_t nprob, const gabi_problem *probs,
         if (staged[k].n == 0) continue;
         auto s = std::make_unique<Slot>();
         s->tag = staged[k].tag;
+        s->ticket = k;
         s->u_out = staged[k].u_out;
         s->bytes = staged[k].bytes;
         s->t_submit = s->t_admit = 0.0;
@@ -607,6 +613,7 @@ int gabi_server_submit(gabi_server *srv, const gabi_problem *p, int64_t *ticket)
         return GABI_EBUSY;
     }
     st->t_submit = srv->clock();
+    st->ticket = srv->seq;
     if (ticket) *ticket = srv->seq;
     srv->seq++;
     srv->queue.push_back(std::move(st));

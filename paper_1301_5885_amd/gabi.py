@@ -83,7 +83,8 @@ class ProblemC(C.Structure):
 class ResultC(C.Structure):
     _fields_ = [("tag", C.c_int64), ("status", C.c_int32), ("energy", C.c_double),
                 ("info", SolveInfo), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_done", C.c_double), ("device_bytes", C.c_int64)]
+                ("t_done", C.c_double), ("device_bytes", C.c_int64),
+                ("ticket", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "info"}
@@ -509,15 +510,22 @@ class Server:
         if rc != OK:
             raise GabiError(rc, "gabi_server_create")
         self._h = h
+        # requests in flight by ticket: the worker may still copy a solution
+        # into req.u, so each Request stays alive until its result is polled
         self._keep = {}
 
     def submit(self, req):
+        """Queues req; returns its ticket (results carry it back)."""
         t = C.c_int64()
         rc = self._lib.gabi_server_submit(self._h, C.byref(req.c), C.byref(t))
         if rc != OK:
             raise GabiError(rc, self._lib.gabi_server_last_error(self._h).decode())
-        self._keep[req.c.tag] = req
+        self._keep[t.value] = req
         return t.value
+
+    def in_flight(self):
+        """Tickets submitted whose results have not been polled yet."""
+        return sorted(self._keep)
 
     def poll(self, max_results=256):
         buf = (ResultC * max_results)()
@@ -526,6 +534,8 @@ class Server:
         if rc != OK:
             raise GabiError(rc, "gabi_server_poll")
         out = [buf[i].as_dict() for i in range(cnt.value)]
+        for r in out:
+            self._keep.pop(r["ticket"], None)
         return out
 
     def drain(self, timeout_s=600.0):

@@ -118,3 +118,28 @@ def test_invalid_request_rejected():
         with pytest.raises(gabi.GabiError) as e:
             s.submit(bad)
         assert e.value.code == gabi.EINVAL
+
+
+def test_duplicate_tags_keep_every_request_alive_until_polled():
+    """Tags are caller values and may repeat: the binding keeps each Request
+    (whose solution buffer the worker may still write) by its ticket until
+    its result has been polled, and results carry the ticket back."""
+    V, F = icosphere(4, 3.0)
+    rng = np.random.default_rng(9)
+    reqs = [gabi.Request.from_mesh(V, F, charges_in_ball(rng, 3, 2.0), rng.normal(size=3),
+                                   tag=7, want_solution=True) for _ in range(5)]
+    with gabi.Server(device=-1, budget_bytes=1 << 30, max_slots=2,
+                     mock_round_seconds=0.002) as s:
+        tickets = [s.submit(r) for r in reqs]
+        assert len(set(tickets)) == 5
+        assert s.in_flight() == sorted(tickets)
+        assert s.drain(60.0)
+        got = []
+        while True:
+            part = s.poll()
+            if not part:
+                break
+            got += part
+        assert sorted(r["ticket"] for r in got) == sorted(tickets)
+        assert all(r["tag"] == 7 for r in got)
+        assert s.in_flight() == []
