@@ -8,21 +8,32 @@ inputs already resident on the device.  The headline solver is FP64
 iterative refinement around FP32-pair GMRES cycles; the plain FP64 GMRES
 solver is timed beside it on the same workload.
 
+The default workload is the largest single-GPU one (sphere, N = 327,680).
+
 Printed (one JSON line on stdout):
   value      Gpair-kernels/s of the mixed solver over the whole step:
              (FP32 + FP64 products) x N(N-1) ordered pairs / wall time.
+  energy_rel_err, potential_err
+             error of the energy and of phi/psi against the oracle's tight
+             solve stored under tests/golden/ (sampled elements where the
+             whole vector is not stored).
   roofline   the FP32-pair product kernel: 61 algorithmic FLOP per ordered
-             pair x N(N-1) per launch / its average launch time (HIP events
-             around every launch on the solver's stream, timed region only)
-             against the published FP32 vector peak.
-  cpu_baseline  the FP64 CPU oracle's product on the host cores.
+             pair x N(N-1) per product / its time per product (HIP events
+             around the product's pair launches in separate event-timed
+             solves) against the published FP32 vector peak; executed_frac
+             is the rocprofv3 VALU FLOP count over the same time.
+  fp64_solver  the plain FP64 GMRES solver on the same workload.
+  secondary  the same figures on a smaller workload (default kirkwood).
+  cpu_baseline  the FP64 CPU oracle on the host cores: product rate, an
+             extrapolated solve time at the workload, a measured solve of
+             the secondary workload.
   serving    solves/s and p50/p99 latency of the plain FP64 solver, the
              plain mixed solver and the served (batched, memory-admitted)
              mixed solver on a stream of uneven requests
              (paper_1301_5885_amd/serve.py).
 
-Usage: python bench.py [--steps K] [--warmup W] [--workload kirkwood]
-                       [--serve-requests 64]
+Usage: python bench.py [--steps K] [--warmup W] [--workload large]
+                       [--serve-requests 512]
 """
 from __future__ import annotations
 
@@ -101,20 +112,51 @@ def valu_from_profiles(kernel_key, workload, avg_s):
             "source": f"rocprofv3 SQ_INSTS_VALU_FLOPS_* (profiles/valu_flops_{workload}.md)"}
 
 
-def golden_energy(workload):
+def golden(workload):
+    """Stored oracle values of the workload (tests/golden/, written by
+    make_golden.py from the CPU oracle alone), or None."""
     path = os.path.join(ROOT, "tests", "golden", f"{workload}_reference.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        return json.load(f)["energy_kcal_per_mol"]
+        return json.load(f)
 
 
-def run_solver(ctx, gabi, torch, u, mode, steps, warmup, pairs):
-    """Two timed passes of `steps` solves (each solve includes its energy):
-    the first with kernel timing off gives the throughput; the second, the
-    same solves with HIP events recorded around every pair-kernel launch
-    (event-record nodes inside the replayed round graphs, which add about
-    3 us per record), gives the kernel durations for the roofline."""
+def potential_errors(u, ref, n):
+    """Error of phi and psi (Section 3.1, eq. (eqerr1): relative error of the
+    surface potential) against the oracle's tight solve: over the whole
+    vector where it is stored, else over its seeded sampled elements."""
+    import numpy as np
+    if ref is None:
+        return None
+    full = ref.get("full_u")
+    if full:
+        path = os.path.join(ROOT, "tests", "golden", full)
+        if os.path.exists(path):
+            r = np.load(path, allow_pickle=False)
+            out = {"over": f"all {n} elements"}
+            for key, a, b in (("phi", u[:n], r[:n]), ("psi", u[n:], r[n:])):
+                out[f"{key}_rel_err"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+                out[f"{key}_max_rel_err"] = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+            return out
+    smp = ref.get("samples")
+    if not smp:
+        return None
+    idx = np.asarray(smp["index"], dtype=np.int64)
+    out = {"over": f"{idx.size} sampled elements (seed {smp['seed']})"}
+    for key, a, b in (("phi", u[idx], np.asarray(smp["phi"])),
+                      ("psi", u[n + idx], np.asarray(smp["psi"]))):
+        out[f"{key}_rel_err"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        out[f"{key}_max_rel_err"] = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    return out
+
+
+def run_solver(ctx, gabi, torch, u, mode, steps, warmup, event_solves, pairs):
+    """`steps` timed solves (each with its energy) with kernel timing off give
+    the throughput; then `event_solves` more solves of the same problem with
+    HIP events recorded around every product's pair-kernel launches
+    (event-record nodes inside the replayed round graphs, about 3 us per
+    record) give the kernel durations for the roofline."""
     for _ in range(warmup):
         ctx.solve_dev(u, tol=TOL, mode=mode)
         ctx.energy_dev(None)
@@ -126,13 +168,14 @@ def run_solver(ctx, gabi, torch, u, mode, steps, warmup, pairs):
         energies.append(ctx.energy_dev(None))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    u_host = u.cpu().numpy()
     for prec in (gabi.FP64, gabi.FP32_PAIR):
         ctx.kernel_time(prec, reset=True)
     ctx.set_kernel_timing(True)
     timed_infos = []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(event_solves):
         timed_infos.append(ctx.solve_dev(u, tol=TOL, mode=mode))
         ctx.energy_dev(None)
     torch.cuda.synchronize()
@@ -145,12 +188,14 @@ def run_solver(ctx, gabi, torch, u, mode, steps, warmup, pairs):
     p64 = sum(i["matvecs_fp64"] for i in infos)
     p32 = sum(i["matvecs_fp32"] for i in infos)
     return {
-        "elapsed": elapsed, "infos": infos, "energies": energies,
+        "steps": steps, "elapsed": elapsed, "infos": infos, "energies": energies,
+        "u": u_host,
         "products_fp64": p64, "products_fp32": p32,
         "gpairs_per_s": (p64 + p32) * pairs / elapsed / 1e9,
         "solves_per_s": steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
-        "timed_pass_ms_per_step": 1e3 * elapsed_timed / steps,
+        "event_solves": event_solves,
+        "timed_pass_ms_per_step": 1e3 * elapsed_timed / max(1, event_solves),
         "timed_products_fp64": sum(i["matvecs_fp64"] for i in timed_infos),
         "timed_products_fp32": sum(i["matvecs_fp32"] for i in timed_infos),
         "kernel_total_ms": {k: v[0] * v[1] for k, v in kt.items()},
@@ -162,9 +207,9 @@ def roofline(res, key, n, workload, gabi=None):
     products = res["timed_products_fp32" if key == "fp32" else "timed_products_fp64"]
     if products == 0:
         return None
-    # every launch of the timed pass is timed; launches skipped after an early
-    # stop of a cycle last a few microseconds and are charged to the real
-    # products
+    # every product of the event pass is timed (from before its first pair
+    # launch to after its last); launches skipped after an early stop of a
+    # cycle last a few microseconds and are charged to the real products
     avg_s = res["kernel_total_ms"][key] / products / 1e3
     flop = FLOP_PER_PAIR * n * (n - 1)
     achieved = flop / avg_s / 1e12
@@ -176,67 +221,106 @@ def roofline(res, key, n, workload, gabi=None):
     mixed = "true" if key == "fp32" else "false"
     kname = (f"gabi::sym_pair_kernel<{mixed}>" if scheme == gabi.SCHEME_SYMMETRIC
              else f"gabi::pair_kernel<{mixed}, {R}>")
+    hw = valu_from_profiles(key, workload, avg_s)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": t,
-            "hw_valu": valu_from_profiles(key, workload, avg_s),
+            "executed_frac": hw["frac"] if hw else None,
+            "hw_valu": hw,
             "kernel": kname, "scheme": "symmetric" if scheme else "split",
             "target_blocks": blocks, "tail_pieces": tail,
             "avg_launch_ms": round(avg_s * 1e3, 5),
             "flop_per_launch": flop,
-            "timing": "HIP events around every pair-kernel launch in a second timed pass "
-                      f"of the same solves ({res['timed_pass_ms_per_step']:.3f} ms/step with "
-                      "the event records)"}
+            "flop_basis": "algorithmic: 61 FLOP per ordered pair x N(N-1) per product; "
+                          "executed_frac is the rocprofv3 VALU FLOP count of the same "
+                          "kernel over this duration",
+            "timing": f"HIP events around the pair-kernel launches of every product in "
+                      f"{res['event_solves']} further solves of the same problem "
+                      f"({res['timed_pass_ms_per_step']:.3f} ms/solve with the event records)"}
 
 
-def cpu_baseline(problem, seconds):
-    """The FP64 oracle's product on the host cores: whole products when one
-    takes at most `seconds` at about 1 Gpair/s, else rows of it (each row is
-    a full sum over all sources, the same work per pair)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _rows_rate(oracle, el, u, args, seconds, rng_seed, threads=None):
+    """Gpair-kernels/s of the oracle's product on random rows (each row a
+    full sum over all sources)."""
+    import numpy as np
+    rate_guess = 1e9 if threads is None else 0.08e9 * threads
+    nrows = int(max(16, min(2 * el.n, seconds * rate_guess / 3 / (el.n - 1))))
+    rows = np.random.default_rng(rng_seed).choice(2 * el.n, nrows, replace=False)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.matvec_rows(el, u, rows, *args)
+        reps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return reps * nrows * (el.n - 1) / dt / 1e9, f"{reps} samples of {nrows} random rows, " \
+                                                  f"{dt:.1f} s wall"
+
+
+def cpu_baseline(problem, seconds, fp64_products, small=None):
+    """The FP64 CPU oracle on the host cores.
+
+    value: Gpair-kernels/s of its product (rows of the workload's product;
+    each row is a full sum over all sources), built as the CPU-baseline plan
+    says (-O3 -march=native, no contraction: bitwise the default build).
+    solve: the oracle's time for one whole solve of the workload, extrapolated
+    as (products of an FP64 GMRES(10) solve at the bench tolerance) x (product
+    time) + the source-term and energy sums at the same pair rate; small: one
+    measured oracle solve (rhs + GMRES + energy) of a smaller workload."""
     import numpy as np
     import oracle
     el = oracle.mesh_elements(problem.V, problem.F)
     u = np.random.default_rng(0).normal(size=2 * el.n)
     args = (problem.eps1, problem.eps2, problem.kappa)
-    full = el.n * (el.n - 1) <= seconds * 1e9
-    if full:
-        unit_pairs = el.n * (el.n - 1)
-        run = lambda: oracle.matvec(el, u, *args)
-        what = f"full FP64 products of the workload (N={el.n}, {unit_pairs} ordered pairs each)"
-    else:
-        nrows = int(max(64, min(2 * el.n, seconds * 1e9 / 4 / (el.n - 1))))
-        rows = np.random.default_rng(1).choice(2 * el.n, nrows, replace=False)
-        unit_pairs = nrows * (el.n - 1)
-        run = lambda: oracle.matvec_rows(el, u, rows, *args)
-        what = (f"samples of {nrows} random rows of the FP64 product (N={el.n}, "
-                f"{unit_pairs} ordered pairs each)")
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        run()
-        reps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    elapsed = time.perf_counter() - t0
-    out = {"value": round(reps * unit_pairs / elapsed / 1e9, 5), "unit": "Gpair-kernels/s",
-           "cores": oracle.num_threads(), "kind": "oracle",
-           "sample": f"{reps} {what}, {elapsed:.1f} s wall"}
-    # the same oracle on one core, to set beside single-core CPU figures
     cores = oracle.num_threads()
-    nrows1 = int(max(16, min(2 * el.n, seconds * 0.25 * 0.08e9 / (el.n - 1))))
-    rows1 = np.random.default_rng(2).choice(2 * el.n, nrows1, replace=False)
-    oracle.set_num_threads(1)
+    out = {"unit": "Gpair-kernels/s", "cores": cores, "kind": "oracle",
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+    oracle.use_native_build(True)
     try:
-        reps1, t1 = 0, time.perf_counter()
-        while True:
-            oracle.matvec_rows(el, u, rows1, *args)
-            reps1 += 1
-            if time.perf_counter() - t1 >= seconds * 0.25:
-                break
-        el1 = time.perf_counter() - t1
+        rate, what = _rows_rate(oracle, el, u, args, seconds * 0.5, 1)
+        out["value"] = round(rate, 5)
+        out["build"] = "gcc " + " ".join(oracle.NATIVE_FLAGS) + " -fopenmp"
+        out["sample"] = f"{what} of the FP64 product (N={el.n})"
+        oracle.set_num_threads(1)
+        try:
+            r1, w1 = _rows_rate(oracle, el, u, args, seconds * 0.15, 2, threads=1)
+        finally:
+            oracle.set_num_threads(cores)
+        out["one_core"] = {"value": round(r1, 5), "sample": w1}
     finally:
-        oracle.set_num_threads(cores)
-    out["one_core"] = {"value": round(reps1 * nrows1 * (el.n - 1) / el1 / 1e9, 5),
-                       "sample": f"{reps1} samples of {nrows1} random rows, {el1:.1f} s wall"}
+        oracle.use_native_build(False)
+    r2, w2 = _rows_rate(oracle, el, u, args, seconds * 0.2, 3)
+    out["default_build"] = {"value": round(r2, 5), "build": "gcc -O2 -fopenmp", "sample": w2}
+    pairs = el.n * (el.n - 1)
+    src_pairs = 2 * el.n * problem.nc  # source terms + energy sums, about 1 pair each
+    t_solve = (fp64_products * pairs + src_pairs) / (rate * 1e9)
+    out["solve"] = {"kind": "extrapolated", "seconds_per_solve": round(t_solve, 3),
+                    "solves_per_s": round(1.0 / t_solve, 6), "products": fp64_products,
+                    "basis": "products of the GPU FP64 GMRES(10) solve at the bench tolerance "
+                             "(the oracle's count agrees within one at the stored workloads) "
+                             "x the measured product rate"}
+    if small is not None:
+        ps = small
+        els = oracle.mesh_elements(ps.V, ps.F)
+        t0 = time.perf_counter()
+        _, E, info = oracle.solve(els, ps.pos, ps.q, ps.eps1, ps.eps2, ps.kappa,
+                                  restart=10, tol=TOL, maxit=1000)
+        ts = time.perf_counter() - t0
+        out["small_solve"] = {"workload": f"N={els.n}, Nc={len(ps.q)}", "kind": "measured",
+                              "seconds_per_solve": round(ts, 3),
+                              "solves_per_s": round(1.0 / ts, 5),
+                              "products": info["matvecs"], "build": "gcc -O2 -fopenmp"}
     return out
 
 
@@ -276,21 +360,72 @@ def warm_sequence(ctx, gabi, p, steps):
             "max_energy_rel_diff_warm_vs_cold": max(abs(a / b - 1) for a, b in zip(ew, ec))}
 
 
+def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves):
+    """Mixed and FP64 solves of one workload on one context."""
+    from paper_1301_5885_amd.synth import config_problem
+    t0 = time.perf_counter()
+    p = config_problem(name)
+    n = p.n
+    log(f"[bench] workload {name} N={n} Nc={p.nc} (generated in "
+        f"{time.perf_counter() - t0:.1f} s)")
+    ctx = gabi.Context(0)
+    ctx.load_problem(p)
+    u = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    ref = golden(name)
+    E_ref = ref["energy_kcal_per_mol"] if ref else None
+    results = {}
+    for key, mode, k, w in (("mixed", gabi.SOLVE_MIXED_IR, steps, warmup),
+                            ("fp64", gabi.SOLVE_FP64, fp64_steps, min(warmup, 1))):
+        log(f"[bench] {name} {key}: {w} warmup + {k} timed + {event_solves} event-timed solves")
+        r = run_solver(ctx, gabi, torch, u, mode, k, w, event_solves, n * (n - 1))
+        E = r["energies"][-1]
+        r["energy"] = E
+        r["energy_rel_err"] = abs(E / E_ref - 1) if E_ref else None
+        r["potential_err"] = potential_errors(r["u"], ref, n)
+        results[key] = r
+        log(f"[bench] {name} {key}: {r['ms_per_step']:.3f} ms/solve, "
+            f"{r['gpairs_per_s']:.1f} Gpairs/s, E={E:.8f}, err={r['energy_rel_err']}, "
+            f"potential {r['potential_err']}")
+    mixed, fp64 = results["mixed"], results["fp64"]
+    solver_line = lambda r, key: {
+        "value": round(r["gpairs_per_s"], 3), "unit": "Gpair-kernels/s",
+        "solves_per_s": round(r["solves_per_s"], 4), "ms_per_step": round(r["ms_per_step"], 4),
+        "steps": r["steps"],
+        "energy": r["energy"], "energy_rel_err": r["energy_rel_err"],
+        "potential_err": r["potential_err"],
+        "products_per_solve": {"fp32": r["products_fp32"] / r["steps"],
+                               "fp64": r["products_fp64"] / r["steps"]},
+        "roofline": roofline(r, key, n, name, gabi)}
+    out = {"workload": WORKLOADS[name], "key": name, "N": n, "Nc": p.nc,
+           "oracle_reference": (f"tests/golden/{name}_reference.json (oracle GMRES to "
+                                f"{ref['tol']:g})") if ref else None,
+           "mixed": solver_line(mixed, "fp32"), "fp64_solver": solver_line(fp64, "fp64"),
+           "speedup_mixed_over_fp64": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3)}
+    return ctx, p, out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="kirkwood", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="timed solves of the plain FP64 solver beside the headline "
+                         "(at most --steps)")
+    ap.add_argument("--event-solves", type=int, default=2,
+                    help="solves with HIP events around the pair kernels (roofline)")
+    ap.add_argument("--secondary", default="kirkwood",
+                    help="a second, smaller workload timed the same way ('none': skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=64,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving stream to serve after the single-solve "
                          "timing (0: skip; the stream has 512)")
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--sequence-steps", type=int, default=8,
-                    help="nearby problems solved cold and warm-started after the timing "
-                         "(0: skip)")
+                    help="nearby problems solved cold and warm-started after the timing, "
+                         "on the secondary workload (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run one device copy of this many MiB "
                          "(a kernel of known traffic for scaling HBM counters)")
@@ -300,6 +435,7 @@ def main():
               "supported (the row-sharded multi-GPU product is a design only)",
               file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
 
     from paper_1301_5885_amd import serve
     serve_problems = None
@@ -310,12 +446,7 @@ def main():
 
     import torch
     from paper_1301_5885_amd import gabi
-    from paper_1301_5885_amd.synth import config_problem
 
-    p = config_problem(args.workload)
-    n = p.n
-    pairs = n * (n - 1)
-    log(f"[bench] workload {args.workload} N={n} Nc={p.nc}")
     if args.copy_mb:
         a = torch.ones(args.copy_mb * 131072, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -323,70 +454,61 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {args.copy_mb} MiB read + written")
         del a, b
-    ctx = gabi.Context(0)
-    ctx.load_problem(p)
-    u = torch.empty(2 * n, dtype=torch.float64, device="cuda")
-    E_ref = golden_energy(args.workload)
 
-    results = {}
-    for key, mode in (("mixed", gabi.SOLVE_MIXED_IR), ("fp64", gabi.SOLVE_FP64)):
-        log(f"[bench] timing {key}: {args.warmup} warmup + {args.steps} steps")
-        r = run_solver(ctx, gabi, torch, u, mode, args.steps, args.warmup, pairs)
-        E = r["energies"][-1]
-        r["energy"] = E
-        r["energy_rel_err"] = abs(E / E_ref - 1) if E_ref else None
-        results[key] = r
-        log(f"[bench] {key}: {r['ms_per_step']:.3f} ms/step, "
-            f"{r['gpairs_per_s']:.1f} Gpairs/s, E={E:.8f}, err={r['energy_rel_err']}")
-
-    mixed, fp64 = results["mixed"], results["fp64"]
+    fp64_steps = max(1, min(args.fp64_steps, args.steps))
+    ctx, p, head = measure(gabi, torch, args.workload, args.steps, args.warmup, fp64_steps,
+                           args.event_solves)
+    ctx.close()
+    mixed = head["mixed"]
     line = {
         "metric": METRIC,
-        "value": round(mixed["gpairs_per_s"], 3),
+        "value": mixed["value"],
         "unit": "Gpair-kernels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(mixed["ms_per_step"], 4),
+        "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 pair terms, f64 accumulation/Krylov/residual/energy",
         "data": "synthetic (seeded surface and charges)",
-        "config": {"workload": WORKLOADS[args.workload], "N": n, "Nc": p.nc,
+        "config": {"workload": head["workload"], "N": head["N"], "Nc": head["Nc"],
                    "eps1": p.eps1, "eps2": p.eps2, "kappa": p.kappa,
                    "restart": 10, "tol": TOL, "solver": "mixed IR (FP32-pair GMRES "
                    "cycles, FP64 residuals)", "parallelism": "single GPU"},
-        "solves_per_s": round(mixed["solves_per_s"], 3),
+        "solves_per_s": mixed["solves_per_s"],
         "energy_rel_err": mixed["energy_rel_err"],
-        "products_per_solve": {"fp32": mixed["products_fp32"] / args.steps,
-                               "fp64": mixed["products_fp64"] / args.steps},
-        "roofline": roofline(mixed, "fp32", n, args.workload, gabi),
-        "fp64_solver": {
-            "value": round(fp64["gpairs_per_s"], 3), "unit": "Gpair-kernels/s",
-            "solves_per_s": round(fp64["solves_per_s"], 3),
-            "ms_per_step": round(fp64["ms_per_step"], 4),
-            "energy_rel_err": fp64["energy_rel_err"],
-            "products_per_solve": fp64["products_fp64"] / args.steps,
-            "roofline": roofline(fp64, "fp64", n, args.workload, gabi),
-        },
-        "speedup_mixed_over_fp64": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3),
+        "potential_err": mixed["potential_err"],
+        "oracle_reference": head["oracle_reference"],
+        "products_per_solve": mixed["products_per_solve"],
+        "roofline": mixed["roofline"],
+        "fp64_solver": head["fp64_solver"],
+        "speedup_mixed_over_fp64": head["speedup_mixed_over_fp64"],
     }
-    if args.sequence_steps > 0:
-        log(f"[bench] warm-started sequence: {args.sequence_steps} nearby problems")
-        line["warm_sequence"] = warm_sequence(ctx, gabi, p, args.sequence_steps)
-        log(f"[bench] sequence: {line['warm_sequence']}")
-    ctx.close()
+    small = None
+    if args.secondary != "none" and args.secondary != args.workload:
+        ctx2, small, sec = measure(gabi, torch, args.secondary, args.steps, args.warmup,
+                                   args.steps, args.event_solves)
+        line["secondary"] = sec
+        if args.sequence_steps > 0:
+            log(f"[bench] warm-started sequence: {args.sequence_steps} nearby problems")
+            line["warm_sequence"] = warm_sequence(ctx2, gabi, small, args.sequence_steps)
+            line["warm_sequence"]["workload"] = args.secondary
+            log(f"[bench] sequence: {line['warm_sequence']}")
+        ctx2.close()
     if serve_problems is not None:
         log(f"[bench] serving {args.serve_requests} requests")
         line["serving"] = serve.run(args.serve_requests, args.serve_slots,
                                     problems=serve_problems)
         line["serving"]["workload"] = SERVING_WORKLOAD
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline (oracle, ~{args.cpu_seconds:.0f} s)")
-        line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        log(f"[bench] cpu baseline (oracle, ~{args.cpu_seconds:.0f} s + a small solve)")
+        line["cpu_baseline"] = cpu_baseline(
+            p, args.cpu_seconds, head["fp64_solver"]["products_per_solve"]["fp64"], small)
     else:
         line["cpu_baseline"] = None
+    line["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(line), flush=True)
 
 

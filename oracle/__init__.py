@@ -55,6 +55,30 @@ def _load():
     return _lib
 
 
+# Timing-only build of the same source with the flags of the CPU-baseline
+# plan (-O3 -march=native; -ffp-contract=off keeps every product and sum as
+# written, so its results are bitwise those of the default build).
+_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+NATIVE_FLAGS = ["-O3", "-march=native", "-ffp-contract=off"]
+
+
+def use_native_build(enable: bool = True) -> None:
+    """Route later oracle calls to the timing build (enable) or back to the
+    default build.  For timing runs only."""
+    global _lib
+    if not enable:
+        _lib = None
+        _load()
+        return
+    tmp = _NATIVE + f".tmp{os.getpid()}"
+    subprocess.run(["gcc", *NATIVE_FLAGS, "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                    "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, _NATIVE)
+    lib = C.CDLL(_NATIVE)
+    _declare(lib)
+    _lib = lib
+
+
 _dp = C.POINTER(C.c_double)
 _i64 = C.c_int64
 
