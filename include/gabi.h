@@ -204,11 +204,14 @@ int gabi_reaction_potential(gabi_ctx *ctx, const double *u, double *phi);
 /* Device memory held by the context in bytes.                               */
 int64_t gabi_device_bytes(const gabi_ctx *ctx);
 
-/* Average device duration (milliseconds) of the pair-kernel launches of
- * products made since the last reset, measured with HIP events around each
- * launch on the context's stream when timing is enabled (event-record nodes
- * inside a captured round); count receives the number of launches.  Timing
- * adds two event records per product.                                      */
+/* Average device duration (milliseconds) per product of the pair-kernel
+ * launches of products made since the last reset, measured with HIP events
+ * on the context's stream when timing is enabled (from before a product's
+ * first pair launch to after its last, folds between passes included;
+ * event-record nodes inside a captured round); count receives the number
+ * of products.  precision GABI_TIMING_TREE gives the treecode products
+ * (all three of their kernels).  Timing adds two event records per product. */
+#define GABI_TIMING_TREE 2
 int gabi_set_kernel_timing(gabi_ctx *ctx, int enable);
 int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
                      int64_t *count, int reset);
@@ -231,19 +234,23 @@ int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
  *                        and the A, B factors are shared by the (i, j) and
  *                        (j, i) terms (K1 is symmetric; K2..K4 differ only
  *                        in which normal and weights they use).  Diagonal
- *                        blocks (I, I) evaluate their ordered pairs.  Row
- *                        partial sums are kept per 256-source block.  Block
- *                        pairs in the band 1 <= J - I <= tail_pieces are
- *                        taken as two half tiles (128 sources of J each; the
- *                        second half's row sums get slots of their own), so
- *                        short work items fill the device's last round.
- *                        rows_per_thread must be 1; target_blocks is not
- *                        used.
+ *                        blocks (I, I) evaluate their ordered pairs.  The
+ *                        block pairs are taken in the rounds of a
+ *                        round-robin tournament (each block once per
+ *                        round), and each round leaves one partial sum per
+ *                        row.  When a product's rounds need more partial
+ *                        sums than the partial-sum budget holds
+ *                        (gabi_set_part_budget), it runs as several passes
+ *                        of at most that many rounds, each pass folded into
+ *                        an FP64 accumulator before the next.
+ *                        rows_per_thread must be 1; target_blocks and
+ *                        tail_pieces are not used.
  *
  * Work items are taken longest first.  A row's partial sums are added in
- * source order, and the decomposition depends only on N, the precision and
- * this table, so set the table before creating contexts or servers: every
- * solve made under one table is bitwise reproducible, alone or batched.  The
+ * a fixed order, and the decomposition depends only on N, the precision,
+ * this table and the partial-sum budget, so set them before creating
+ * contexts or servers: every solve made under one table and budget is
+ * bitwise reproducible, alone or batched.  The
  * table holds one entry per precision and N bucket (bucket = floor(log2 N),
  * 0..39).  rows_per_thread is 1 or 2; target_blocks in [1, 2^20];
  * tail_pieces in [0, 4096].  GABI_EINVAL otherwise.                          */
@@ -252,6 +259,106 @@ int gabi_tune_set(int precision, int bucket, int scheme, int rows_per_thread,
                   int target_blocks, int tail_pieces);
 int gabi_tune_get(int precision, int bucket, int *scheme, int *rows_per_thread,
                   int *target_blocks, int *tail_pieces);
+
+/* Partial-sum budget: bytes one molecule's partial row sums of one
+ * precision may take (default 512 MiB).  The symmetric scheme keeps
+ * min(nbk, budget / (2 N x 8 bytes FP64, x 4 bytes FP32 pair)) slots per
+ * row, nbk = ceil(N / 256), so a molecule's device memory is O(N) for a
+ * given budget (the paper keeps O(N) device memory, Section 2.4).  Applies
+ * to contexts, batches and servers whose molecules are sized after the
+ * call.  bytes >= 1; GABI_EINVAL otherwise.                                 */
+int gabi_set_part_budget(int64_t bytes);
+int64_t gabi_get_part_budget(void);
+
+/* ------------------------------------------------------------------------ */
+/* Molecular surfaces and charges from files (host only).                   */
+/* ------------------------------------------------------------------------ */
+
+/* The paper's host reads the molecule (atom coordinates, radii, charges)
+ * and the MSMS triangulation of its surface (Section 2.4, table tb_GPU).
+ * MSMS files: <name>.vert (a count line, then "x y z nx ny nz ..." per
+ * vertex, the vertex normal pointing out) and <name>.face (a count line,
+ * then "v1 v2 v3 ..." per triangle, 1-based); lines starting with '#' are
+ * comments.  PQR files: ATOM/HETATM records whose last five fields are
+ * x y z charge radius.  Paths are NUL-terminated; arrays are caller-owned
+ * host memory.  Unreadable file: GABI_EINVAL; malformed record, index out
+ * of range or count mismatch: GABI_EMESH.                                   */
+int gabi_msms_counts(const char *vert_path, const char *face_path, int64_t *nv, int64_t *nf);
+/* xyz: 3 nv doubles; vnormal: 3 nv doubles or null; tri: 3 nf 0-based
+ * vertex indices (as gabi_set_surface_mesh takes them).                    */
+int gabi_msms_read(const char *vert_path, const char *face_path, int64_t nv, double *xyz,
+                   double *vnormal, int64_t nf, int32_t *tri);
+/* Rewinds every triangle whose right-hand normal points against the mean of
+ * its vertex normals, so that all are counter-clockwise seen from outside
+ * (the orientation gabi_set_surface_mesh assumes); *flipped receives how
+ * many were rewound.                                                        */
+int gabi_msms_orient(int64_t nv, const double *xyz, const double *vnormal, int64_t nf,
+                     int32_t *tri, int64_t *flipped);
+int gabi_pqr_count(const char *path, int64_t *natoms);
+/* xyz: 3 natoms doubles, q: natoms charges (e), radius: natoms or null.     */
+int gabi_pqr_read(const char *path, int64_t natoms, double *xyz, double *q, double *radius);
+
+/* ------------------------------------------------------------------------ */
+/* Treecode approximation of the product.                                   */
+/* ------------------------------------------------------------------------ */
+
+/* The paper evaluates the product by direct summation, O(N^2), and names
+ * tree codes, O(N log N), as the route to larger surfaces (Section 1;
+ * Section 4).  This is the barycentric Lagrange treecode of Wang, Krasny and
+ * Tlupova (Commun. Comput. Phys. 28, 2020), particle-cluster form with
+ * target batches, in FP64:
+ *   - the centroids are split recursively (minimal boxes, cut at the box
+ *     midpoint in every dimension of at least 1/sqrt 2 of the largest
+ *     extent) down to leaves of at most leaf_size elements, the batches;
+ *   - a cluster C acts on a batch B through (degree+1)^3 proxy points (the
+ *     tensor Chebyshev points of the second kind of its box, carrying
+ *     weights interpolated from its elements with barycentric Lagrange
+ *     bases) when (r_B + r_C) < theta R (radii of the boxes, R the distance
+ *     of their centres) and C has more elements than proxies; directly when
+ *     the criterion holds and it has fewer; else through its children (a
+ *     leaf directly).
+ * theta in [0, 1) (0: every pair directly, the exact product up to
+ * summation order), degree in [1, 8], leaf_size in [1, 256]; GABI_EINVAL
+ * otherwise.  The tree is built on the host at the first product after the
+ * surface or the options change and kept on the device.                    */
+typedef struct {
+    double theta;
+    int32_t degree;
+    int32_t leaf_size;
+} gabi_tree_opts;
+
+typedef struct {
+    int64_t leaves;                 /* target batches                        */
+    int64_t clusters_with_proxies;  /* clusters acting through proxies       */
+    int64_t far_entries, near_entries;  /* interaction-list entries          */
+    int64_t far_pairs, near_pairs;  /* (target, proxy) and (target, element)
+                                       pairs per product (near pairs include
+                                       each batch's own diagonal)            */
+    int64_t device_bytes;           /* device memory of the tree data        */
+} gabi_tree_info;
+
+/* y = A u approximated by the treecode, as gabi_matvec (host vectors of 2N
+ * doubles) and gabi_matvec_dev (device vectors, on the context's stream).
+ * Needs the surface and the parameters (GABI_ESTATE otherwise).           */
+int gabi_tree_matvec(gabi_ctx *ctx, const gabi_tree_opts *opts, const double *u,
+                     double *y);
+int gabi_tree_matvec_dev(gabi_ctx *ctx, const gabi_tree_opts *opts,
+                         const double *u_dev, double *y_dev);
+/* Statistics of the context's tree for these options (builds it).          */
+int gabi_tree_info_get(gabi_ctx *ctx, const gabi_tree_opts *opts, gabi_tree_info *out);
+/* The same statistics from centroids alone, on the host (no device).       */
+int gabi_tree_plan(int64_t n, const double *cx, const double *cy, const double *cz,
+                   const gabi_tree_opts *opts, gabi_tree_info *out);
+
+/* ------------------------------------------------------------------------ */
+/* Self-test of device arithmetic.                                          */
+/* ------------------------------------------------------------------------ */
+
+/* The FP64 e^{-t} the pair kernels use (the exponential of the screened
+ * Coulomb kernel, Section 2.1 eq. (eq_potential), in K1..K4 of eq. (Eq_Ls)),
+ * evaluated on `device` at n host values 0 <= t (finite) into out (host);
+ * for accuracy tests.  GABI_EINVAL for bad arguments.                       */
+int gabi_selftest_exp_neg(int device, int64_t n, const double *t, double *out);
 
 /* ------------------------------------------------------------------------ */
 /* Many molecules at once.                                                  */
@@ -339,6 +446,15 @@ int gabi_server_poll(gabi_server *srv, gabi_result *out, int32_t max, int32_t *c
 /* Blocks until every submitted request has finished or timeout_s elapses;
  * GABI_EBUSY on timeout.                                                   */
 int gabi_server_drain(gabi_server *srv, double timeout_s);
+/* Round cap, for latency of the largest requests: each round runs the
+ * oldest active request and, in admission order, each further one whose
+ * work (N^2) keeps the round's total within
+ * max((1 + slack) x the oldest's work, floor_elements^2); the others wait a
+ * round.  slack < 0 (the default) runs every active request every round.
+ * Results do not depend on it (a request's arithmetic is the same in any
+ * round).  Takes effect from the next round.  GABI_EINVAL for a non-finite
+ * slack or a negative floor.                                                */
+int gabi_server_set_round_cap(gabi_server *srv, double slack, int64_t floor_elements);
 int gabi_server_stats_get(gabi_server *srv, gabi_server_stats *out);
 /* Seconds on the server's monotonic clock (the clock of gabi_result).      */
 double gabi_server_clock(gabi_server *srv);

@@ -387,13 +387,15 @@ void gabi_destroy(gabi_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 3; ++p)
         for (auto &ev : ctx->pending[p]) {
             (void)hipEventDestroy(ev.first);
             (void)hipEventDestroy(ev.second);
         }
     batch_free(ctx->batch);
     free_slot(ctx);
+    tree_free(ctx->tree);
+    if (ctx->tree_u) (void)hipFree(ctx->tree_u);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     delete ctx;
 }
@@ -467,6 +469,7 @@ int gabi_set_surface(gabi_ctx *ctx, int64_t n, const double *cx,
     }
     ctx->n = n;
     ctx->geom_dirty = true;
+    ctx->geom_version++;
     ctx->have_solution = false;
     return GABI_OK;
 }
@@ -716,9 +719,9 @@ int gabi_set_kernel_timing(gabi_ctx *ctx, int enable) {
 int gabi_kernel_time(gabi_ctx *ctx, int precision, double *avg_ms,
                      int64_t *count, int reset) {
     if (!ctx) return GABI_EINVAL;
-    if (precision != GABI_FP64 && precision != GABI_FP32_PAIR)
+    if (precision != GABI_FP64 && precision != GABI_FP32_PAIR && precision != GABI_TIMING_TREE)
         return fail(ctx, GABI_EINVAL, "unknown precision");
-    const int p = precision == GABI_FP64 ? 0 : 1;
+    const int p = precision == GABI_FP64 ? 0 : precision == GABI_FP32_PAIR ? 1 : 2;
     for (auto &ev : ctx->pending[p]) {
         GABI_HIP(ctx, hipEventSynchronize(ev.second));
         float ms = 0.0f;

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/gabi.h"
+#include "sym_schedule.h"
 
 namespace gabi {
 
@@ -28,18 +29,29 @@ constexpr double kCoulomb = 332.0716;  // kcal A / (mol e^2)
 // Decomposition of one product: row blocks x source splits.  A function of
 // N and the precision (and the loaded tuning table) only.
 // Split scheme: sources [0, tail_start) form `head` splits of tiles_per_split
-// tiles of 256; [tail_start, N) forms splits of kPiece sources.  Symmetric
-// scheme: row_blocks = blocks of 256, head = the band K (block pairs with
-// 1 <= J - I <= K are taken as two half tiles), splits = row_blocks + K.
+// tiles of 256; [tail_start, N) forms splits of kPiece sources; one pass.
+// Symmetric scheme: row_blocks = nbk blocks of 256, whose block pairs are
+// taken in nbk rounds (sym_schedule.h) grouped into `passes` passes of
+// `splits` rounds; a round writes one partial-sum slot per row, so a pass
+// needs `splits` slots (the last pass `last`), and passes after the first
+// fold their slots into an FP64 accumulator.  splits is bounded by the
+// partial-sum budget, so the buffer is O(N) for a given budget.
 struct PairLaunch {
-    int scheme = GABI_SCHEME_SPLIT;  // symmetric: row_blocks = splits = blocks of 256
+    int scheme = GABI_SCHEME_SPLIT;
     int rows_per_thread = 1;
     int row_blocks = 0;
     int tiles_per_split = 0;
-    int splits = 0;
+    int splits = 0;      // partial-sum slots per row (per pass)
     int head = 0;
     int tail_start = 0;
+    int passes = 1;
+    int last = 0;        // slots of the last pass
 };
+
+// Bytes one precision's partial sums of one molecule may take (the
+// symmetric scheme's slots per pass follow from it); library-wide.
+int64_t part_budget();
+void set_part_budget(int64_t bytes);
 
 struct TuneEntry {  // one row of the tuning table
     int scheme = GABI_SCHEME_SPLIT;
@@ -61,6 +73,7 @@ __host__ __device__ inline void split_range(int n, int tps, int head, int tail_s
 }
 
 PairLaunch pair_launch(int64_t n, int precision);
+PairLaunch pair_launch_budget(int64_t n, int precision, int64_t budget);
 int blas_blocks(int64_t n);
 // Tuning table (tune.hip): per precision and N bucket (bucket = floor(log2 N)).
 TuneEntry tune_entry(int precision, int64_t n);
@@ -96,9 +109,10 @@ struct Mol {
     int32_t R32, rb32, tps32, sp32;   // FP32-pair product decomposition
     int32_t head64, tail64, head32, tail32;  // split source ranges (split_range)
     // symmetric scheme per precision (then R = 1, rb = nbk blocks of 256,
-    // headXX = the band K of block pairs split into half tiles, sp = nbk + K
-    // partial slots, and the FP32-pair partial sums are stored as float)
+    // spXX = partial slots per pass, npXX passes, lastXX slots of the last
+    // pass, and the FP32-pair partial sums are stored as float)
     int32_t sym64, sym32, nbk, pad_sym;
+    int32_t np64, np32, last64, last32;
     int32_t rx_kblocks, rx_tps, rx_splits, maxit;
     double kappa, eps, inv_eps, d_top, d_bot, rhs_scale;
     double tol0, inner_tol;             // solve targets (copied into st)
@@ -110,7 +124,8 @@ struct Mol {
     const double4 *chg;   // (x, y, z, q)
     double4 *wgt;         // (s, mx, my, mz)
     float4 *wgt32;
-    double *part;         // split partial sums [splits][2][n]
+    double *part;         // partial sums [slots][2][n] (float: symmetric FP32 pair)
+    double *acc;          // 2n FP64 sums of the passes before the last (or null)
     // vectors of length 2n
     double *u, *y;        // product input / output (matvec entry points)
     double *b, *x, *r, *w, *bo, *xo, *sol;
@@ -155,6 +170,9 @@ int64_t next_slot_uid();
 int64_t slot_bytes(int64_t n, int64_t nc, int m);
 void slot_carve(Slot &s, int64_t n, int64_t nc, int m);
 void slot_set_params(Slot &s, double eps1, double eps2, double kappa);
+void mol_set_params(Mol &M, double eps1, double eps2, double kappa);
+// the product-decomposition fields of a descriptor
+void mol_decomposition(Mol &t, int64_t n, const PairLaunch &L64, const PairLaunch &L32);
 void slot_set_mode(Slot &s, int mode);
 
 // ---------------------------------------------------------------------------
@@ -169,6 +187,10 @@ struct Batch {
     // symmetric scheme (mol, block I, block J, cost): n_tilesXX[0..2] entries
     int4 *d_tiles64 = nullptr; int n_tiles64[3] = {0, 0, 0};
     int4 *d_tiles32 = nullptr; int n_tiles32[3] = {0, 0, 0};
+    // symmetric tiles by pass: pass p is entries [sym_offXX[p], sym_offXX[p+1])
+    // of the symmetric group (the molecules' passes p run in one launch)
+    int n_pass64 = 1, n_pass32 = 1;
+    int sym_off64[kMaxPasses + 1] = {0}, sym_off32[kMaxPasses + 1] = {0};
     int4 *d_rx = nullptr;     int n_rx = 0;     // (mol, charge block, split, 0)
     int *d_counter = nullptr;  // tile queues of the persistent product (4)
     KrylovStatus *d_status = nullptr;  // gathered statuses, one per molecule
@@ -190,8 +212,12 @@ struct Batch {
 };
 
 int batch_build(Batch &b, hipStream_t stream, std::string &err);
+void pair_grids(int g64[3], int g32[3]);  // persistent grids of the pair kernels
 void batch_free(Batch &b);
 void release_graph(Batch &b);  // the captured round and its events
+
+struct TreeState;                // treecode product (tree.hip)
+void tree_free(TreeState *t);
 
 }  // namespace gabi
 
@@ -224,9 +250,19 @@ struct gabi_ctx {
     std::vector<float4> host_geo32;  // pos32 then nrm32 (2n)
 
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
-    double total_ms[2] = {0, 0};
-    int64_t count[2] = {0, 0};
+    // event pairs per timed kind: FP64 products, FP32-pair products,
+    // treecode products
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
+    double total_ms[3] = {0, 0, 0};
+    int64_t count[3] = {0, 0, 0};
+
+    // treecode product: its tree and device data (rebuilt when the surface,
+    // counted by geom_version, or the options change) and the device vectors
+    // of the host entry point
+    gabi::TreeState *tree = nullptr;
+    int64_t geom_version = 0;
+    double *tree_u = nullptr, *tree_y = nullptr;
+    int64_t tree_io_n = 0;
 };
 
 namespace gabi {
@@ -271,6 +307,7 @@ void stage_surface(int64_t n, const double *cx, const double *cy, const double *
 void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);
 void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer *t);
 void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip);
+void launch_fold(const Batch &b, hipStream_t s, int precision, int pass, bool skip);
 int pair_occupancy_grid(int precision, int variant);
 // sources.hip
 void launch_rhs(const Batch &b, hipStream_t s);

@@ -19,8 +19,12 @@
 //           launches one workgroup per tile;
 //   finish  O(N S): adds the split partials in split order, applies the
 //           diagonal, and (inside GMRES) emits the first MGS dot partial.
-// The split count depends only on N and the precision, so a molecule's
-// summation order is the same alone or in any batch (bitwise reproducible).
+// A symmetric product whose partial slots would exceed the partial-sum
+// budget runs as several passes (pair launch, then a fold of the pass's
+// slots into an FP64 accumulator; the finish adds the last pass).
+// The decomposition depends only on N, the precision, the tuning table and
+// the budget, so a molecule's summation order is the same alone or in any
+// batch (bitwise reproducible).
 // The self term j = i is skipped exactly: only the source stages that overlap
 // the tile's own rows run the masked loop.
 #include "arnoldi.h"
@@ -291,7 +295,8 @@ __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
 }
 
 // ------------------------------------------------------------- symmetric
-// Tile (I, J) of the symmetric scheme, one element of block I per thread.
+// Tile (I, J) of the symmetric scheme (I <= J), one element of block I per
+// thread, writing partial-sum slot `slot` of its rows and columns.
 // The workgroup stages block J in LDS (two 4-vectors per element:
 // (x, y, z, s) and (nx, ny, nz, t), where m = t nu), taken in four chunks of
 // 64 elements.  At step s of a chunk lane l reads element (l - s) mod 64, so the
@@ -301,12 +306,14 @@ __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
 //    lane's own row sums, the (j, i) terms to column sums that rotate through
 //    the wave with the read pattern (wave_rotate) and are back in their
 //    home lane after 64 steps.  The four waves' column sums of an element are
-//    added in wave order through LDS.  Row sums go to partial slot J of row
-//    i, column sums to slot I of row j.
+//    added in wave order through LDS.  Row sums go to the tile's slot of row
+//    i, column sums to the same slot of row j.
 //  * I = J: the ordered pairs (i, j), i != j, of the block (row sums only)
-//    go to slot I.
-// Every slot of every row is written by exactly one tile, and the finish adds
-// the slots in block order.  Elements past N (the ragged last block) sit far
+//    go to the tile's slot.
+// The tiles come in rounds in which every block takes part once, and the
+// tiles of round r write slot r mod (slots per pass): every slot of every row
+// is written by exactly one tile of a pass, and the slots are added in round
+// order.  Elements past N (the ragged last block) sit far
 // away (rows and columns on opposite sides) with zero weights, so their terms
 // are exactly zero and every lane takes part in the rotation; their own sums
 // are not stored.
@@ -331,7 +338,7 @@ __device__ __forceinline__ SymElem<typename PairView<MIXED>::T> sym_load(const M
 }
 
 template <bool MIXED>
-__device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
+__device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int slot,
                                          typename PairView<MIXED>::T4 *s_stage) {
     using T = typename PairView<MIXED>::T;
     using T4 = typename PairView<MIXED>::T4;
@@ -353,11 +360,9 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
     }
     __syncthreads();
     T *part = reinterpret_cast<T *>(M.part);  // float for the FP32-pair product
-    // chunks of block J this tile covers: all four, or two for a half tile
-    const int c0 = half == 2 ? 2 : 0, c1 = half == 1 ? 2 : kTile / 64;
     T top = T(0), bot = T(0);
 #pragma unroll 1
-    for (int c = c0; c < c1; ++c) {
+    for (int c = 0; c < kTile / 64; ++c) {
         if (c * 64 >= cnt) break;
         const T4 *ca = sa + c * 128 + lane + 64, *cb = sb + c * 128 + lane + 64;
         if (I == J) {
@@ -418,7 +423,7 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
     }
     if (I != J) {
         __syncthreads();
-        if (tid < cnt && tid >= c0 * 64 && tid < c1 * 64) {
+        if (tid < cnt) {
             const T *cs = reinterpret_cast<const T *>(sa + (tid >> 6) * 128);
             T ct = cs[lane], cbs = cs[kBlock + lane];
 #pragma unroll
@@ -426,24 +431,13 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int half,
                 ct += cs[w * 64 + lane];
                 cbs += cs[kBlock + w * 64 + lane];
             }
-            part[(size_t)(2 * I) * n + jt + tid] = ct;
-            part[(size_t)(2 * I + 1) * n + jt + tid] = cbs;
+            part[(size_t)(2 * slot) * n + jt + tid] = ct;
+            part[(size_t)(2 * slot + 1) * n + jt + tid] = cbs;
         }
     }
     if (act) {
-        // the second half of a band pair has its own slot past the block slots
-        const int nbk = M.nbk;
-        const int slot = half == 2 ? nbk + (J - I - 1) : J;
         part[(size_t)(2 * slot) * n + i] = top;
         part[(size_t)(2 * slot + 1) * n + i] = bot;
-        if (I == J) {
-            // band slots of this block without a partner block stay zero
-            const int band = (MIXED ? M.sp32 : M.sp64) - nbk;
-            for (int d = nbk - 1 - I; d < band; ++d) {
-                part[(size_t)(2 * (nbk + d)) * n + i] = T(0);
-                part[(size_t)(2 * (nbk + d) + 1) * n + i] = T(0);
-            }
-        }
     }
 }
 
@@ -461,8 +455,7 @@ __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
          t = next_tile(persistent, t, ntiles, counter, &s_next)) {
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
-        if (!(skip && load_done(M.st)))
-            sym_tile<MIXED>(M, tile.y, tile.z & 0xffffff, tile.z >> 24, s_stage);
+        if (!(skip && load_done(M.st))) sym_tile<MIXED>(M, tile.y, tile.z, tile.w & 0xffff, s_stage);
     }
 }
 
@@ -470,6 +463,8 @@ __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
 // MODE kFinishDot: w = D V_j - sum part, partials of <w, V_0>
 //      kFinishRes: res_out = res_b - (D res_x - sum part), partials of ||.||^2
 //      kFinishY:   y = D u - sum part
+// where sum part = the slots of the product's last pass, preceded by the
+// FP64 sums of its earlier passes when it has several.
 // A workgroup of kFinishQ x 256 threads covers 256 elements per pass: thread
 // group q adds the partial slots [q S / kFinishQ, (q+1) S / kFinishQ) of its
 // element in slot order, and the groups' sums are added in group order, so
@@ -520,7 +515,8 @@ __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
     if (skip && load_done(M.st)) return;
     const int n = M.n, nb = M.nb;
     const int q = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
-    const int splits = precision == GABI_FP64 ? M.sp64 : M.sp32;
+    const int splits = precision == GABI_FP64 ? M.last64 : M.last32;
+    const bool multi = (precision == GABI_FP64 ? M.np64 : M.np32) > 1;
     const int p0 = q * splits / kFinishQ, p1 = (q + 1) * splits / kFinishQ;
     const double *v = MODE == kFinishDot ? M.V + (size_t)j * 2 * n
                     : MODE == kFinishRes ? M.res_x
@@ -550,6 +546,10 @@ __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
                 st += acc[0][r][t];
                 sb += acc[1][r][t];
             }
+            if (multi) {
+                st = M.acc[i] + st;
+                sb = M.acc[n + i] + sb;
+            }
             double yt = dt * v[i] - st;
             double yb = db * v[n + i] - sb;
             if constexpr (MODE == kFinishRes) {
@@ -568,6 +568,57 @@ __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
     if constexpr (MODE != kFinishY) {
         s = block_sum(s, lds);
         if (threadIdx.x == 0) M.red[e.y] = s;
+    }
+}
+
+// ------------------------------------------------------------------ fold
+// After pass `pass` of a symmetric product taken in several passes (not its
+// last): acc = (acc of the earlier passes, if any) + the pass's slots, added
+// as the finish adds them.  Also rearms the symmetric tile queue of this
+// precision for the next pass's launch.
+__global__ __launch_bounds__(kBlock * kFinishQ) void fold_kernel(
+    const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision, int pass,
+    int skip, int *__restrict__ counters) {
+    __shared__ double accs[2][kFinishQ - 1][kBlock];
+    if (blockIdx.x == 0 && threadIdx.x == 0) counters[2] = 0;
+    const int2 e = list[blockIdx.x];
+    const Mol &M = mols[e.x];
+    if (skip && load_done(M.st)) return;
+    const int np = precision == GABI_FP64 ? M.np64 : M.np32;
+    if (pass >= np - 1) return;
+    const int n = M.n, nb = M.nb;
+    const int q = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
+    const int splits = precision == GABI_FP64 ? M.sp64 : M.sp32;
+    const int p0 = q * splits / kFinishQ, p1 = (q + 1) * splits / kFinishQ;
+    const float *pf = reinterpret_cast<const float *>(M.part);
+    for (int base = e.y * kBlock; base < n; base += nb * kBlock) {
+        const int i = base + t;
+        double st = 0.0, sb = 0.0;
+        if (i < n) {
+            if (precision != GABI_FP64)  // several passes: the symmetric scheme
+                sum_slots(pf, n, i, p0, p1, st, sb);
+            else
+                sum_slots(static_cast<const double *>(M.part), n, i, p0, p1, st, sb);
+        }
+        if (q > 0) {
+            accs[0][q - 1][t] = st;
+            accs[1][q - 1][t] = sb;
+        }
+        __syncthreads();
+        if (q == 0 && i < n) {
+#pragma unroll
+            for (int r = 0; r < kFinishQ - 1; ++r) {
+                st += accs[0][r][t];
+                sb += accs[1][r][t];
+            }
+            if (pass > 0) {
+                st = M.acc[i] + st;
+                sb = M.acc[n + i] + sb;
+            }
+            M.acc[i] = st;
+            M.acc[n + i] = sb;
+        }
+        __syncthreads();
     }
 }
 
@@ -600,6 +651,7 @@ static void pair_group(Batch &b, hipStream_t s, const int4 *tiles, int ntiles, i
                        int grid_cap, bool skip) {
     if (ntiles == 0) return;
     // the counter is zero: set by the batch upload, rearmed by every finish
+    // (and, for the symmetric queue, by the fold between passes)
     const int grid = b.persistent ? std::min(ntiles, grid_cap) : ntiles;
     if constexpr (R == 0)
         hipLaunchKernelGGL((sym_pair_kernel<MIXED>), dim3(grid), dim3(kBlock), 0, s, b.d_mols,
@@ -650,11 +702,21 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
     if (mixed) {
         pair_group<true, 2>(b, s, tiles, cnt[0], c, b.grid32[0], skip);
         pair_group<true, 1>(b, s, t1, cnt[1], c + 1, b.grid32[1], skip);
-        pair_group<true, 0>(b, s, t2, cnt[2], c + 2, b.grid32[2], skip);
     } else {
         pair_group<false, 2>(b, s, tiles, cnt[0], c, b.grid64[0], skip);
         pair_group<false, 1>(b, s, t1, cnt[1], c + 1, b.grid64[1], skip);
-        pair_group<false, 0>(b, s, t2, cnt[2], c + 2, b.grid64[2], skip);
+    }
+    // symmetric tiles pass by pass, each pass but the last folded into the
+    // accumulator before the next reuses the slots
+    const int *off = mixed ? b.sym_off32 : b.sym_off64;
+    const int passes = mixed ? b.n_pass32 : b.n_pass64;
+    for (int p = 0; p < passes; ++p) {
+        const int a = off[p], z = off[p + 1];
+        if (mixed)
+            pair_group<true, 0>(b, s, t2 + a, z - a, c + 2, b.grid32[2], skip);
+        else
+            pair_group<false, 0>(b, s, t2 + a, z - a, c + 2, b.grid64[2], skip);
+        if (p + 1 < passes) launch_fold(b, s, precision, p, skip);
     }
     if (e0 && e1) {
         record_event(e1, s);
@@ -674,6 +736,12 @@ void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j
     else
         hipLaunchKernelGGL(finish_kernel<kFinishY>, g, blk, 0, s, b.d_mols, b.d_blas,
                            precision, j, (int)skip, c);
+}
+
+void launch_fold(const Batch &b, hipStream_t s, int precision, int pass, bool skip) {
+    int *c = b.d_counter + (precision == GABI_FP64 ? 0 : 4);
+    hipLaunchKernelGGL(fold_kernel, dim3(b.n_blas), dim3(kBlock * kFinishQ), 0, s, b.d_mols,
+                       b.d_blas, precision, pass, (int)skip, c);
 }
 
 template <typename K>

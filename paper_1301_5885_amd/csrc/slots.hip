@@ -11,6 +11,14 @@
 
 namespace gabi {
 
+// ------------------------------------------------------- partial-sum budget
+namespace {
+std::atomic<int64_t> g_part_budget{int64_t(512) << 20};
+}
+
+int64_t part_budget() { return g_part_budget.load(); }
+void set_part_budget(int64_t bytes) { g_part_budget.store(bytes); }
+
 // ---------------------------------------------------------------- tuning
 namespace {
 constexpr int kBuckets = 40;
@@ -64,6 +72,10 @@ void reset_tuning() {
 }
 
 PairLaunch pair_launch(int64_t n, int precision) {
+    return pair_launch_budget(n, precision, part_budget());
+}
+
+PairLaunch pair_launch_budget(int64_t n, int precision, int64_t budget) {
     const TuneEntry e = tune_entry(precision, n);
     PairLaunch L;
     L.scheme = e.scheme;
@@ -71,8 +83,10 @@ PairLaunch pair_launch(int64_t n, int precision) {
         L.rows_per_thread = 1;
         L.row_blocks = (int)((n + kTile - 1) / kTile);
         L.tiles_per_split = 1;
-        L.head = std::min(e.tail_pieces, std::max(0, L.row_blocks - 1));  // the band
-        L.splits = L.row_blocks + L.head;
+        L.head = 0;
+        const int64_t slot_bytes = 2 * n * (precision == GABI_FP64 ? 8 : 4);
+        sym_passes(L.row_blocks, budget / std::max<int64_t>(1, slot_bytes), L.passes, L.splits);
+        L.last = L.row_blocks - (L.passes - 1) * L.splits;
         L.tail_start = (int)n;
         return L;
     }
@@ -92,6 +106,8 @@ PairLaunch pair_launch(int64_t n, int precision) {
     L.tiles_per_split = (int)tps;
     L.head = (int)((tiles + tps - 1) / tps);
     L.splits = L.head + (int)((n - tail_start + kPiece - 1) / kPiece);
+    L.passes = 1;
+    L.last = L.splits;
     return L;
 }
 
@@ -107,6 +123,14 @@ extern "C" int gabi_tune_set(int precision, int bucket, int scheme, int rows_per
     e.tail_pieces = tail_pieces;
     return gabi::set_tune_entry(precision, bucket, e);
 }
+
+extern "C" int gabi_set_part_budget(int64_t bytes) {
+    if (bytes < 1) return GABI_EINVAL;
+    gabi::set_part_budget(bytes);
+    return GABI_OK;
+}
+
+extern "C" int64_t gabi_get_part_budget(void) { return gabi::part_budget(); }
 
 extern "C" int gabi_tune_get(int precision, int bucket, int *scheme, int *rows_per_thread,
                              int *target_blocks, int *tail_pieces) {
@@ -152,6 +176,32 @@ void reaction_split(int64_t n, int64_t nc, int &kblocks, int &tps, int &splits) 
     splits = (int)((tiles + t - 1) / t);
 }
 
+}  // namespace
+
+void mol_decomposition(Mol &t, int64_t n, const PairLaunch &L64, const PairLaunch &L32) {
+    t.R64 = L64.rows_per_thread;
+    t.rb64 = L64.row_blocks;
+    t.tps64 = L64.tiles_per_split;
+    t.sp64 = L64.splits;
+    t.R32 = L32.rows_per_thread;
+    t.rb32 = L32.row_blocks;
+    t.tps32 = L32.tiles_per_split;
+    t.sp32 = L32.splits;
+    t.head64 = L64.head;
+    t.tail64 = L64.tail_start;
+    t.head32 = L32.head;
+    t.tail32 = L32.tail_start;
+    t.sym64 = L64.scheme == GABI_SCHEME_SYMMETRIC;
+    t.sym32 = L32.scheme == GABI_SCHEME_SYMMETRIC;
+    t.np64 = L64.passes;
+    t.np32 = L32.passes;
+    t.last64 = L64.last;
+    t.last32 = L32.last;
+    t.nbk = (int32_t)((n + kTile - 1) / kTile);
+}
+
+namespace {
+
 // Lays the buffers of one molecule out in one block starting at base (null:
 // sizing only); returns the size in bytes.
 int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
@@ -173,6 +223,8 @@ int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
     const int64_t part64 = len * L64.splits * 8;
     const int64_t part32 = len * L32.splits * (L32.scheme == GABI_SCHEME_SYMMETRIC ? 4 : 8);
     t.part = c.take<double>((std::max(part64, part32) + 7) / 8);
+    // sums of the earlier passes of a product taken in several passes
+    t.acc = (L64.passes > 1 || L32.passes > 1) ? c.take<double>(len) : nullptr;
     t.u = c.take<double>(len);
     t.y = c.take<double>(len);
     t.b = c.take<double>(len);
@@ -198,21 +250,7 @@ int64_t layout(int64_t n, int64_t nc, int m, char *base, Mol *M) {
         t.nc = (int32_t)nc;
         t.nb = blas_blocks(n);
         t.m = m;
-        t.R64 = L64.rows_per_thread;
-        t.rb64 = L64.row_blocks;
-        t.tps64 = L64.tiles_per_split;
-        t.sp64 = L64.splits;
-        t.R32 = L32.rows_per_thread;
-        t.rb32 = L32.row_blocks;
-        t.tps32 = L32.tiles_per_split;
-        t.sp32 = L32.splits;
-        t.head64 = L64.head;
-        t.tail64 = L64.tail_start;
-        t.head32 = L32.head;
-        t.tail32 = L32.tail_start;
-        t.sym64 = L64.scheme == GABI_SCHEME_SYMMETRIC;
-        t.sym32 = L32.scheme == GABI_SCHEME_SYMMETRIC;
-        t.nbk = (int32_t)((n + kTile - 1) / kTile);
+        mol_decomposition(t, n, L64, L32);
         t.rx_kblocks = kb;
         t.rx_tps = tps;
         t.rx_splits = sp;
@@ -239,7 +277,10 @@ void slot_carve(Slot &s, int64_t n, int64_t nc, int m) {
 }
 
 void slot_set_params(Slot &s, double eps1, double eps2, double kappa) {
-    Mol &M = s.mol;
+    mol_set_params(s.mol, eps1, eps2, kappa);
+}
+
+void mol_set_params(Mol &M, double eps1, double eps2, double kappa) {
     const double eps = eps2 / eps1;
     M.kappa = kappa;
     M.eps = eps;
@@ -315,6 +356,24 @@ void batch_free(Batch &b) {
     b.d_mols = nullptr;
     b.n_elem = b.n_blas = b.n_rx = 0;
     for (int g = 0; g < 3; ++g) b.n_tiles64[g] = b.n_tiles32[g] = 0;
+    b.n_pass64 = b.n_pass32 = 1;
+    std::memset(b.sym_off64, 0, sizeof(b.sym_off64));
+    std::memset(b.sym_off32, 0, sizeof(b.sym_off32));
+}
+
+void pair_grids(int g64[3], int g32[3]) {
+    static int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int v = 0; v < 3; ++v) {
+            grid[0][v] = pair_occupancy_grid(GABI_FP64, v);
+            grid[1][v] = pair_occupancy_grid(GABI_FP32_PAIR, v);
+        }
+    });
+    for (int v = 0; v < 3; ++v) {
+        g64[v] = grid[0][v];
+        g32[v] = grid[1][v];
+    }
 }
 
 int batch_build(Batch &b, hipStream_t stream, std::string &err) {
@@ -329,23 +388,18 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         for (int i = 0; i < eb; ++i) elem.push_back(make_int2(k, i));
         for (int i = 0; i < M.nb; ++i) blas.push_back(make_int2(k, i));
         // split scheme: (mol, row block, split, cost = rows per thread x
-        // sources); symmetric scheme: (mol, block I, J | half << 24, cost) for
-        // J >= I, half = 0 a whole pair (cost two diagonal tiles), 1 and 2 the
-        // two halves of a pair in the band 1 <= J - I <= K (cost one each)
+        // sources); symmetric scheme: (mol, block I, block J, slot | pass << 16)
+        // for the tiles of every round in round order (sym_schedule.h), round
+        // r in pass r / sp writing slot r mod sp
         auto tiles = [&](std::vector<int4> &t, int sym, int R, int rb, int sp, int tps, int head,
                          int tail) {
             if (sym) {
-                for (int I = 0; I < M.nbk; ++I)
-                    for (int J = I; J < M.nbk; ++J) {
-                        if (J == I) {
-                            t.push_back(make_int4(k, I, J, kTile));
-                        } else if (J - I <= head) {
-                            t.push_back(make_int4(k, I, J | (1 << 24), kTile));
-                            t.push_back(make_int4(k, I, J | (2 << 24), kTile));
-                        } else {
-                            t.push_back(make_int4(k, I, J, 2 * kTile));
-                        }
-                    }
+                std::vector<std::pair<int, int>> rt;
+                for (int r = 0; r < M.nbk; ++r) {
+                    sym_round(M.nbk, r, rt);
+                    const int w = (r % sp) | ((r / sp) << 16);
+                    for (const auto &pr : rt) t.push_back(make_int4(k, pr.first, pr.second, w));
+                }
                 return;
             }
             for (int s = 0; s < sp; ++s) {
@@ -361,19 +415,23 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
                 for (int kb = 0; kb < M.rx_kblocks; ++kb) rx.push_back(make_int4(k, kb, sp, 0));
     }
     // group by kernel variant (split with two rows per thread, split with one,
-    // symmetric), longest tiles first within a group; ties keep molecule and
-    // tile order
-    // (a stable counting sort over the few distinct (group, cost) keys: a
-    // comparison sort of a large batch's tiles took milliseconds per rebuild)
-    auto group = [&](std::vector<int4> &t, bool mixed, int *counts) {
+    // symmetric), the symmetric tiles by pass, longest tiles first within a
+    // group or pass; ties keep molecule and tile order
+    // (a stable counting sort over the few distinct (group, pass, cost) keys:
+    // a comparison sort of a large batch's tiles took milliseconds per rebuild)
+    auto group = [&](std::vector<int4> &t, bool mixed, int *counts, std::vector<int> &sym_off) {
         std::vector<int> gm((size_t)nm);
         for (int k = 0; k < nm; ++k) {
             const Mol &M = b.slots[k]->mol;
             gm[k] = (mixed ? M.sym32 : M.sym64) ? 2 : (mixed ? M.R32 : M.R64) == 2 ? 0 : 1;
         }
-        // ascending key = group ascending, then cost descending
+        // ascending key = group ascending, then pass ascending, then cost
+        // descending (a symmetric tile costs two diagonal ones)
         auto key = [&](const int4 &a) {
-            return ((int64_t)gm[a.x] << 32) | (int64_t)(0x7fffffff - a.w);
+            const int g = gm[a.x];
+            const int64_t pass = g == 2 ? (a.w >> 16) : 0;
+            const int64_t cost = g == 2 ? (a.y == a.z ? kTile : 2 * kTile) : a.w;
+            return ((int64_t)g << 56) | (pass << 32) | (int64_t)(0x7fffffff - cost);
         };
         // consecutive tiles mostly share a key, so the map is consulted only
         // when the key changes
@@ -411,11 +469,23 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         }
         t.swap(out);
         counts[0] = counts[1] = counts[2] = 0;
-        for (const int4 &a : t) counts[gm[a.x]]++;
+        std::vector<int> per_pass;  // symmetric tiles of each pass
+        for (const int4 &a : t) {
+            const int g = gm[a.x];
+            counts[g]++;
+            if (g == 2) {
+                const size_t pass = (size_t)(a.w >> 16);
+                if (per_pass.size() <= pass) per_pass.resize(pass + 1, 0);
+                per_pass[pass]++;
+            }
+        }
+        sym_off.assign(1, 0);
+        for (int c : per_pass) sym_off.push_back(sym_off.back() + c);
     };
     int c64[3], c32[3];
-    group(t64, false, c64);
-    group(t32, true, c32);
+    std::vector<int> off64, off32;
+    group(t64, false, c64, off64);
+    group(t32, true, c32, off32);
 
     auto al = [](int64_t v) { return (v + 255) & ~int64_t(255); };
     const int64_t o_mols = 0;
@@ -469,6 +539,13 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         b.n_tiles64[g] = c64[g];
         b.n_tiles32[g] = c32[g];
     }
+    auto set_off = [](const std::vector<int> &off, int *dst, int &np) {
+        np = std::max<int>(1, (int)off.size() - 1);
+        for (int p = 0; p <= kMaxPasses; ++p)
+            dst[p] = p < (int)off.size() ? off[p] : (off.empty() ? 0 : off.back());
+    };
+    set_off(off64, b.sym_off64, b.n_pass64);
+    set_off(off32, b.sym_off32, b.n_pass32);
     b.n_rx = (int)rx.size();
     // stage everything in the pinned buffer, one upload
     char *h = reinterpret_cast<char *>(b.h_pinned);
@@ -486,18 +563,7 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
         return GABI_EDEVICE;
     }
     b.h_status = reinterpret_cast<KrylovStatus *>(h + o_st);
-    static int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    static std::once_flag once;
-    std::call_once(once, [] {
-        for (int v = 0; v < 3; ++v) {
-            grid[0][v] = pair_occupancy_grid(GABI_FP64, v);
-            grid[1][v] = pair_occupancy_grid(GABI_FP32_PAIR, v);
-        }
-    });
-    for (int v = 0; v < 3; ++v) {
-        b.grid64[v] = grid[0][v];
-        b.grid32[v] = grid[1][v];
-    }
+    pair_grids(b.grid64, b.grid32);
     return GABI_OK;
 }
 

@@ -10,8 +10,9 @@ last round.  This module times the whole product (pair kernel plus the
 ordered split reduction) on geodesic spheres of one representative size per
 N bucket (bucket = floor(log2 N)), for both pair precisions: first every
 (R, target_blocks) without a tail, then the three fastest of those with
-each tail length, and the symmetric scheme with each band of half tiles, and
-writes the fastest entry per bucket as JSON.  The
+each tail length, and the symmetric scheme (whose block pairs come in
+round-robin rounds; it has no shape parameter here: its passes follow from
+the partial-sum budget), and writes the fastest entry per bucket as JSON.  The
 library applies that table when it is loaded (`gabi.TUNING_PATH`).
 
 The decomposition fixes the order of the row sums, so a table change
@@ -37,7 +38,7 @@ ROWS = (1, 2)
 TARGET_BLOCKS = (256, 512, 1024, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576, 32768,
                  49152, 65536, 98304, 131072, 196608, 262144)
 TAILS = (4, 8, 16, 32, 64, 128)
-BANDS = (0, 4, 8, 16, 24, 32, 48, 64)   # symmetric scheme: block pairs taken as half tiles
+BANDS = (0,)   # the symmetric scheme's one candidate
 PRECISIONS = {"fp64": gabi.FP64, "fp32": gabi.FP32_PAIR}
 
 

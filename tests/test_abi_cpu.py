@@ -123,10 +123,68 @@ def test_footprint_follows_the_decomposition():
             gabi.tune_set(p, b, gabi.SCHEME_SYMMETRIC, 1, 1, 0)
         sym = gabi.solve_footprint(20480, 200, 10)
         assert sym - small == (80 - 1) * 2 * 20480 * 8
-        # a band of 16 half-tiled block pairs adds 16 slots per row
+        # tail_pieces does not change the symmetric scheme
         for p in (gabi.FP64, gabi.FP32_PAIR):
             gabi.tune_set(p, b, gabi.SCHEME_SYMMETRIC, 1, 1, 16)
-        assert gabi.solve_footprint(20480, 200, 10) - sym == 16 * 2 * 20480 * 8
+        assert gabi.solve_footprint(20480, 200, 10) == sym
+        # a budget of 20 FP64 slots: 4 passes of 20 rounds, 20 slots per row
+        # and an FP64 accumulator of 2N
+        budget = gabi.get_part_budget()
+        try:
+            gabi.set_part_budget(20 * 2 * 20480 * 8)
+            assert gabi.solve_footprint(20480, 200, 10) - small == \
+                (20 - 1) * 2 * 20480 * 8 + 2 * 20480 * 8
+        finally:
+            gabi.set_part_budget(budget)
     finally:
         for p, e in zip((gabi.FP64, gabi.FP32_PAIR), saved):
             gabi.tune_set(p, b, *e)
+
+
+@pytest.mark.parametrize("theta,degree,leaf", [(0.7, 4, 64), (0.5, 6, 128), (0.8, 2, 256),
+                                               (0.0, 3, 100)])
+def test_tree_plan_matches_the_treecode_oracle(theta, degree, leaf):
+    """The library's host tree builder and interaction lists (tree.hip) and
+    the oracle's own implementation of the same rules give the same tree:
+    leaves, proxy clusters, list entries and pair counts agree exactly."""
+    import oracle.treecode as tc
+    rng = np.random.default_rng(5)
+    V, F, _ = star_surface(12, 9.0, rng)
+    el = oracle.mesh_elements(V, F)
+    got = gabi.tree_plan(el.centroids, theta, degree, leaf)
+    _, st = tc.matvec(el, rng.normal(size=2 * el.n), theta=theta, degree=degree, leaf=leaf,
+                      stats=True)
+    assert got["leaves"] == st.leaves
+    assert got["clusters_with_proxies"] == st.clusters_with_proxies
+    assert got["far_entries"] == st.far_entries and got["near_entries"] == st.near_entries
+    assert got["far_pairs"] == st.far_pairs and got["near_pairs"] == st.near_pairs
+
+
+def test_tree_plan_rejects_bad_options():
+    c = np.random.default_rng(0).normal(size=(50, 3))
+    for bad in [dict(theta=1.0), dict(theta=-0.1), dict(degree=0), dict(degree=9),
+                dict(leaf_size=0), dict(leaf_size=257)]:
+        kw = dict(theta=0.5, degree=3, leaf_size=16)
+        kw.update(bad)
+        with pytest.raises(gabi.GabiError):
+            gabi.tree_plan(c, **kw)
+
+
+def test_part_budget_bounds_the_footprint():
+    """The partial-sum budget bounds a molecule's device memory: at the
+    default budget a 327,680-element solve holds well under 1 GB, and the
+    footprint grows about linearly in N beyond the size where the budget
+    binds."""
+    base = gabi.get_part_budget()
+    assert base == 512 << 20
+    f_large = gabi.solve_footprint(327680, 5000, 10)
+    assert f_large < 1 << 30
+    f_2x = gabi.solve_footprint(4 * 327680, 5000, 10)
+    assert f_2x < 4 * f_large * 1.05   # linear, not quadratic
+    try:
+        gabi.set_part_budget(1 << 20)
+        assert gabi.solve_footprint(327680, 5000, 10) < f_large
+    finally:
+        gabi.set_part_budget(base)
+    with pytest.raises(gabi.GabiError):
+        gabi.set_part_budget(0)
