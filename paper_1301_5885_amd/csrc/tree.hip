@@ -1,0 +1,626 @@
+// Treecode approximation of the boundary-integral product y = A u of
+// arXiv:1301.5885 (Section 2.2, eqs. (eqdbef1)/(eqdbef2)); the paper names
+// tree codes, O(N log N), as the route past its O(N^2) direct sum
+// (Section 1; Section 4).  The method is the barycentric Lagrange treecode
+// (BLTC) of Wang, Krasny and Tlupova (Commun. Comput. Phys. 28, 2020) in
+// its particle-cluster form with target batches:
+//
+//  * tree (host): the element centroids are split recursively; a node keeps
+//    the minimal box of its points and, with more than `leaf` points, is cut
+//    at the box midpoint in every dimension whose extent is at least 1/sqrt 2
+//    of the largest (points with coordinate >= midpoint go up); children are
+//    kept in the order of their bit codes, empty ones dropped.  Elements are
+//    renumbered in depth-first leaf order (increasing index within a leaf),
+//    so every node is a contiguous range.  Leaves are the target batches.
+//  * proxies: a cluster with more than P = (n+1)^3 elements that acts on
+//    some batch through interpolation carries the tensor Chebyshev points of
+//    the second kind of its box and modified weights
+//    W_k = sum_{j in C} L_k(y_j) w_j, L_k the product of barycentric Lagrange
+//    bases, w_j = (s_j, m_j) the element's weights of the product.
+//  * interactions (host): for batch B each cluster C is visited from the
+//    root; (r_B + r_C)^2 < theta^2 R^2 makes C act through its proxies (or
+//    directly when it has at most P elements), else a leaf acts directly and
+//    an inner node hands over to its children.
+//
+// Per product three kernels run: weights in tree order (tree_prep), the
+// modified weights (tree_weights, one workgroup per proxy cluster), and the
+// sums (tree_eval, one workgroup per batch, one target per thread, the
+// batch's sources staged through LDS 256 records at a time; the same pair
+// arithmetic as the direct product, FP64).  Every sum is taken in a fixed
+// order, so results are reproducible bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#include "gabi_internal.h"
+#include "pair_math.h"
+
+namespace gabi {
+
+constexpr int kTreeMaxDeg = 8;        // P <= 729 proxies per cluster
+constexpr int kTreeMaxLeaf = kBlock;  // a batch fits one workgroup
+
+struct TreeNode {
+    double lo[3], hi[3];
+    int begin = 0, end = 0;  // range in tree order
+    std::vector<int> children;
+    int proxy = -1;          // index of its proxy cluster, if it has one
+};
+
+struct TreeState {
+    // what the tree was built for
+    int64_t version = -1;
+    double theta = -1.0;
+    int degree = -1, leaf = -1;
+    // host
+    std::vector<TreeNode> nodes;
+    std::vector<int> perm;  // tree position -> element index
+    gabi_tree_info info{};
+    int n = 0, P = 0, n_clusters = 0, n_batches = 0;
+    double bary[kTreeMaxDeg + 1] = {0};
+    // device block
+    void *mem = nullptr;
+    int64_t bytes = 0;
+    double4 *spos = nullptr, *snrm = nullptr, *sw = nullptr, *ppos = nullptr, *pw = nullptr;
+    int *perm_d = nullptr;
+    double *cheb = nullptr;   // 3 (n+1) nodes per cluster
+    int4 *clusters = nullptr;  // (begin, end, proxy offset, 0)
+    int4 *batches = nullptr;   // (begin, end, list offset, list length)
+    int4 *list = nullptr;      // (0 near | 1 far, begin, end, 0)
+};
+
+namespace {
+
+int build_node(TreeState &T, const double4 *pos, std::vector<int> idx, int leaf) {
+    const int id = (int)T.nodes.size();
+    T.nodes.emplace_back();
+    {
+        TreeNode &nd = T.nodes[id];
+        for (int d = 0; d < 3; ++d) {
+            nd.lo[d] = INFINITY;
+            nd.hi[d] = -INFINITY;
+        }
+        for (int j : idx) {
+            const double c[3] = {pos[j].x, pos[j].y, pos[j].z};
+            for (int d = 0; d < 3; ++d) {
+                nd.lo[d] = std::min(nd.lo[d], c[d]);
+                nd.hi[d] = std::max(nd.hi[d], c[d]);
+            }
+        }
+        nd.begin = (int)T.perm.size();
+    }
+    double ext[3], mid[3], L = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        ext[d] = T.nodes[id].hi[d] - T.nodes[id].lo[d];
+        mid[d] = (T.nodes[id].lo[d] + T.nodes[id].hi[d]) / 2.0;
+        L = std::max(L, ext[d]);
+    }
+    if ((int)idx.size() <= leaf || L == 0.0) {
+        T.perm.insert(T.perm.end(), idx.begin(), idx.end());
+        T.nodes[id].end = (int)T.perm.size();
+        return id;
+    }
+    int dims[3], nd = 0;
+    for (int d = 0; d < 3; ++d)
+        if (ext[d] >= L / std::sqrt(2.0)) dims[nd++] = d;
+    std::vector<std::vector<int>> parts((size_t)1 << nd);
+    for (int j : idx) {
+        const double c[3] = {pos[j].x, pos[j].y, pos[j].z};
+        int code = 0;
+        for (int t = 0; t < nd; ++t)
+            if (c[dims[t]] >= mid[dims[t]]) code |= 1 << t;
+        parts[(size_t)code].push_back(j);
+    }
+    for (auto &p : parts) {
+        if (p.empty()) continue;
+        const int child = build_node(T, pos, std::move(p), leaf);
+        T.nodes[id].children.push_back(child);
+    }
+    T.nodes[id].end = (int)T.perm.size();
+    return id;
+}
+
+void centre_radius(const TreeNode &nd, double c[3], double &r) {
+    double h[3];
+    for (int d = 0; d < 3; ++d) {
+        c[d] = (nd.lo[d] + nd.hi[d]) / 2.0;
+        h[d] = (nd.hi[d] - nd.lo[d]) / 2.0;
+    }
+    r = std::sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+}
+
+// Builds the tree, the interaction lists and the statistics on the host.
+// Outputs the lists as (kind, node) pairs per batch.
+void plan(TreeState &T, const double4 *pos, int64_t n, double theta, int degree, int leaf,
+          std::vector<int> &batch_nodes, std::vector<std::vector<std::pair<int, int>>> &lists) {
+    T.nodes.clear();
+    T.perm.clear();
+    T.nodes.reserve((size_t)(4 * n / std::max(1, leaf) + 16));
+    std::vector<int> all((size_t)n);
+    for (int64_t j = 0; j < n; ++j) all[(size_t)j] = (int)j;
+    build_node(T, pos, std::move(all), leaf);
+    T.n = (int)n;
+    T.P = (degree + 1) * (degree + 1) * (degree + 1);
+    batch_nodes.clear();
+    for (int i = 0; i < (int)T.nodes.size(); ++i)
+        if (T.nodes[(size_t)i].children.empty()) batch_nodes.push_back(i);
+    // leaves in tree order (their ranges increase)
+    std::sort(batch_nodes.begin(), batch_nodes.end(),
+              [&](int a, int b) { return T.nodes[(size_t)a].begin < T.nodes[(size_t)b].begin; });
+    lists.assign(batch_nodes.size(), {});
+    gabi_tree_info info{};
+    info.leaves = (int64_t)batch_nodes.size();
+    const double th2 = theta * theta;
+    int n_clusters = 0;
+    for (size_t b = 0; b < batch_nodes.size(); ++b) {
+        const TreeNode &B = T.nodes[(size_t)batch_nodes[b]];
+        double cb[3], rb;
+        centre_radius(B, cb, rb);
+        const int64_t nb = B.end - B.begin;
+        auto &lst = lists[b];
+        std::function<void(int)> visit = [&](int ci) {
+            TreeNode &C = T.nodes[(size_t)ci];
+            double cc[3], rc;
+            centre_radius(C, cc, rc);
+            const double d0 = cb[0] - cc[0], d1 = cb[1] - cc[1], d2 = cb[2] - cc[2];
+            const double R2 = d0 * d0 + d1 * d1 + d2 * d2;
+            const double rr = rb + rc;
+            const int64_t cnt = C.end - C.begin;
+            if (rr * rr < th2 * R2) {
+                if (cnt > T.P) {
+                    if (C.proxy < 0) C.proxy = n_clusters++;
+                    lst.emplace_back(1, ci);
+                    info.far_entries++;
+                    info.far_pairs += (int64_t)T.P * nb;
+                } else {
+                    lst.emplace_back(0, ci);
+                    info.near_entries++;
+                    info.near_pairs += cnt * nb;
+                }
+            } else if (C.children.empty()) {
+                lst.emplace_back(0, ci);
+                info.near_entries++;
+                info.near_pairs += cnt * nb;
+            } else {
+                for (int ch : C.children) visit(ch);
+            }
+        };
+        visit(0);
+    }
+    info.clusters_with_proxies = n_clusters;
+    T.n_clusters = n_clusters;
+    T.n_batches = (int)batch_nodes.size();
+    T.info = info;
+}
+
+int validate_tree_opts(const gabi_tree_opts *o, std::string &msg) {
+    if (!o) {
+        msg = "null treecode options";
+        return GABI_EINVAL;
+    }
+    if (!(o->theta >= 0.0 && o->theta < 1.0)) {
+        msg = "theta must be in [0, 1)";
+        return GABI_EINVAL;
+    }
+    if (o->degree < 1 || o->degree > kTreeMaxDeg) {
+        msg = "degree must be in [1, " + std::to_string(kTreeMaxDeg) + "]";
+        return GABI_EINVAL;
+    }
+    if (o->leaf_size < 1 || o->leaf_size > kTreeMaxLeaf) {
+        msg = "leaf_size must be in [1, " + std::to_string(kTreeMaxLeaf) + "]";
+        return GABI_EINVAL;
+    }
+    return GABI_OK;
+}
+
+// Chebyshev points of the second kind of a cluster's box, per dimension
+// (flat dimensions widened to 1e-6 of the largest half-width).
+void cheb_nodes(const TreeNode &C, int degree, double *out) {
+    double hw[3], mid[3], big = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        hw[d] = (C.hi[d] - C.lo[d]) / 2.0;
+        mid[d] = (C.lo[d] + C.hi[d]) / 2.0;
+        big = std::max(big, hw[d]);
+    }
+    for (int d = 0; d < 3; ++d) {
+        const double h = std::max(hw[d], 1e-6 * big);
+        for (int k = 0; k <= degree; ++k)
+            out[d * (degree + 1) + k] = mid[d] + h * std::cos(k * kPi / degree);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ kernels
+struct TreeDev {
+    const double4 *spos, *snrm;
+    double4 *sw;
+    const double4 *ppos;
+    double4 *pw;
+    const int *perm;
+    const double *cheb;
+    const int4 *clusters, *batches, *list;
+    int n, degree, P;
+    double bary[kTreeMaxDeg + 1];
+};
+
+// Weights of the product in tree order: s = W psi/(4 pi), m = W phi nu/(4 pi).
+__global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const double *__restrict__ u) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= T.n) return;
+    const int j = T.perm[p];
+    const double4 q = T.spos[p], nu = T.snrm[p];
+    const double c = q.w * (1.0 / (4.0 * kPi));
+    const double s = c * u[T.n + j], t = c * u[j];
+    T.sw[p] = make_double4(s, t * nu.x, t * nu.y, t * nu.z);
+}
+
+// Modified weights of one proxy cluster: W_k = sum_j L_k(y_j) w_j over the
+// cluster's elements in tree order.  The 1-D bases of 64 elements are formed
+// at a time (one (element, dimension) per thread), then each thread adds the
+// chunk's terms to its proxies k = tid, tid + 256, ...
+constexpr int kTreeChunk = 64;
+constexpr int kTreeProxPerThread = (729 + kBlock - 1) / kBlock;
+
+__global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T) {
+    __shared__ double s_l[3][kTreeChunk][kTreeMaxDeg + 1];
+    __shared__ double4 s_w[kTreeChunk];
+    const int4 cl = T.clusters[blockIdx.x];
+    const int deg = T.degree, np1 = deg + 1;
+    const double *nodes = T.cheb + (size_t)blockIdx.x * 3 * np1;
+    double4 acc[kTreeProxPerThread];
+#pragma unroll
+    for (int r = 0; r < kTreeProxPerThread; ++r) acc[r] = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int c0 = cl.x; c0 < cl.y; c0 += kTreeChunk) {
+        const int cnt = min(kTreeChunk, cl.y - c0);
+        __syncthreads();
+        if (threadIdx.x < 3 * kTreeChunk) {
+            const int e = threadIdx.x / 3, d = threadIdx.x % 3;
+            if (e < cnt) {
+                const double4 q = T.spos[c0 + e];
+                const double y = d == 0 ? q.x : d == 1 ? q.y : q.z;
+                const double *s = nodes + d * np1;
+                int hit = -1;
+                double sum = 0.0;
+                for (int k = 0; k < np1; ++k) {
+                    const double diff = y - s[k];
+                    if (diff == 0.0 && hit < 0) hit = k;
+                    const double qk = T.bary[k] / diff;
+                    s_l[d][e][k] = qk;
+                    sum += qk;
+                }
+                for (int k = 0; k < np1; ++k)
+                    s_l[d][e][k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : s_l[d][e][k] / sum;
+            }
+        } else if (threadIdx.x - 3 * kTreeChunk < cnt) {
+            const int e = threadIdx.x - 3 * kTreeChunk;
+            s_w[e] = T.sw[c0 + e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kTreeProxPerThread; ++r) {
+            const int k = threadIdx.x + r * kBlock;
+            if (k >= T.P) break;
+            const int k1 = k / (np1 * np1), k2 = (k / np1) % np1, k3 = k % np1;
+            double4 a = acc[r];
+            for (int e = 0; e < cnt; ++e) {
+                const double L = s_l[0][e][k1] * s_l[1][e][k2] * s_l[2][e][k3];
+                const double4 w = s_w[e];
+                a.x = __builtin_fma(L, w.x, a.x);
+                a.y = __builtin_fma(L, w.y, a.y);
+                a.z = __builtin_fma(L, w.z, a.z);
+                a.w = __builtin_fma(L, w.w, a.w);
+            }
+            acc[r] = a;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kTreeProxPerThread; ++r) {
+        const int k = threadIdx.x + r * kBlock;
+        if (k < T.P) T.pw[(size_t)cl.z + k] = acc[r];
+    }
+}
+
+// The sums of one batch: its targets (one per thread) against the sources of
+// its interaction list in list order (near: elements, the target itself
+// skipped; far: proxies), then y = D u - sums at the elements' own indices.
+__global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF64 pc,
+                                                          double d_top, double d_bot,
+                                                          const double *__restrict__ u,
+                                                          double *__restrict__ y) {
+    __shared__ double4 s_pos[kBlock];
+    __shared__ double4 s_w[kBlock];
+    const int4 bt = T.batches[blockIdx.x];
+    const int p = bt.x + (int)threadIdx.x;
+    const bool act = p < bt.y;
+    const int pc_ = act ? p : bt.x;
+    const double4 x = T.spos[pc_], nu = T.snrm[pc_];
+    double top = 0.0, bot = 0.0;
+    for (int e = bt.z; e < bt.z + bt.w; ++e) {
+        const int4 it = T.list[e];
+        const bool far = it.x == 1;
+        const double4 *src_p = far ? T.ppos : T.spos;
+        const double4 *src_w = far ? T.pw : T.sw;
+        for (int j0 = it.y; j0 < it.z; j0 += kBlock) {
+            const int cnt = min(kBlock, it.z - j0);
+            __syncthreads();
+            if ((int)threadIdx.x < cnt) {
+                s_pos[threadIdx.x] = src_p[j0 + threadIdx.x];
+                s_w[threadIdx.x] = src_w[j0 + threadIdx.x];
+            }
+            __syncthreads();
+            const bool self = !far && j0 < bt.y && j0 + cnt > bt.x;
+            if (!self) {
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const double4 q = s_pos[jj], w = s_w[jj];
+                    pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
+                             w.w, top, bot);
+                }
+            } else {
+                for (int jj = 0; jj < cnt; ++jj) {
+                    if (j0 + jj == p) continue;
+                    const double4 q = s_pos[jj], w = s_w[jj];
+                    pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
+                             w.w, top, bot);
+                }
+            }
+        }
+    }
+    if (act) {
+        const int j = T.perm[p];
+        y[j] = d_top * u[j] - top;
+        y[T.n + j] = d_bot * u[T.n + j] - bot;
+    }
+}
+
+// ------------------------------------------------------------------ host
+void tree_free(TreeState *T) {
+    if (!T) return;
+    if (T->mem) (void)hipFree(T->mem);
+    delete T;
+}
+
+namespace {
+
+// Device vectors u, y of 2N doubles for the host entry point (one block).
+int tree_io_buffers(gabi_ctx *ctx) {
+    if (ctx->tree_u && ctx->tree_io_n == ctx->n) return GABI_OK;
+    if (ctx->stream) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->tree_u) (void)hipFree(ctx->tree_u);
+    ctx->tree_u = ctx->tree_y = nullptr;
+    ctx->tree_io_n = 0;
+    hipError_t e = hipMalloc(&ctx->tree_u, sizeof(double) * 4 * (size_t)ctx->n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->tree_u = nullptr;
+        return fail(ctx, GABI_ENOMEM, "treecode vector allocation failed");
+    }
+    ctx->tree_y = ctx->tree_u + 2 * ctx->n;
+    ctx->tree_io_n = ctx->n;
+    return GABI_OK;
+}
+
+// (Re)builds the tree, its lists and device data when the surface or the
+// options changed.
+int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
+    std::string msg;
+    int rc = validate_tree_opts(o, msg);
+    if (rc) return fail(ctx, rc, msg);
+    if (!ctx->tree) ctx->tree = new (std::nothrow) TreeState();
+    if (!ctx->tree) return fail(ctx, GABI_ENOMEM, "treecode state allocation failed");
+    TreeState &T = *ctx->tree;
+    if (T.version == ctx->geom_version && T.theta == o->theta && T.degree == o->degree &&
+        T.leaf == o->leaf_size && T.mem)
+        return GABI_OK;
+    const int64_t n = ctx->n;
+    const double4 *pos = ctx->host_pos.data();
+    const double4 *nrm = ctx->host_nrm.data();
+    std::vector<int> batch_nodes;
+    std::vector<std::vector<std::pair<int, int>>> lists;
+    plan(T, pos, n, o->theta, o->degree, o->leaf_size, batch_nodes, lists);
+    const int deg = o->degree, np1 = deg + 1;
+    for (int k = 0; k <= deg; ++k)
+        T.bary[k] = (k % 2 ? -1.0 : 1.0) * ((k == 0 || k == deg) ? 0.5 : 1.0);
+    // host images of the device arrays
+    std::vector<double4> spos((size_t)n), snrm((size_t)n);
+    for (int64_t p = 0; p < n; ++p) {
+        spos[(size_t)p] = pos[T.perm[(size_t)p]];
+        snrm[(size_t)p] = nrm[T.perm[(size_t)p]];
+    }
+    const int nc = T.n_clusters;
+    std::vector<double> cheb((size_t)nc * 3 * np1);
+    std::vector<int4> clusters((size_t)nc);
+    std::vector<double4> ppos((size_t)nc * T.P);
+    for (const TreeNode &C : T.nodes) {
+        if (C.proxy < 0) continue;
+        double *cn = cheb.data() + (size_t)C.proxy * 3 * np1;
+        cheb_nodes(C, deg, cn);
+        clusters[(size_t)C.proxy] = make_int4(C.begin, C.end, C.proxy * T.P, 0);
+        for (int k = 0; k < T.P; ++k) {
+            const int k1 = k / (np1 * np1), k2 = (k / np1) % np1, k3 = k % np1;
+            ppos[(size_t)C.proxy * T.P + k] =
+                make_double4(cn[k1], cn[np1 + k2], cn[2 * np1 + k3], 0.0);
+        }
+    }
+    std::vector<int4> batches(batch_nodes.size()), list;
+    for (size_t b = 0; b < batch_nodes.size(); ++b) {
+        const TreeNode &B = T.nodes[(size_t)batch_nodes[b]];
+        batches[b] = make_int4(B.begin, B.end, (int)list.size(), (int)lists[b].size());
+        for (auto &kn : lists[b]) {
+            const TreeNode &C = T.nodes[(size_t)kn.second];
+            if (kn.first == 1)
+                list.push_back(make_int4(1, C.proxy * T.P, C.proxy * T.P + T.P, 0));
+            else
+                list.push_back(make_int4(0, C.begin, C.end, 0));
+        }
+    }
+    // one device block
+    auto al = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+    const int64_t o_spos = 0;
+    const int64_t o_snrm = al(o_spos + 32 * n);
+    const int64_t o_sw = al(o_snrm + 32 * n);
+    const int64_t o_ppos = al(o_sw + 32 * n);
+    const int64_t o_pw = al(o_ppos + 32 * std::max<int64_t>(1, (int64_t)ppos.size()));
+    const int64_t o_perm = al(o_pw + 32 * std::max<int64_t>(1, (int64_t)ppos.size()));
+    const int64_t o_cheb = al(o_perm + 4 * n);
+    const int64_t o_cl = al(o_cheb + 8 * std::max<int64_t>(1, (int64_t)cheb.size()));
+    const int64_t o_bt = al(o_cl + 16 * std::max<int64_t>(1, (int64_t)nc));
+    const int64_t o_li = al(o_bt + 16 * (int64_t)batches.size());
+    const int64_t total = al(o_li + 16 * std::max<int64_t>(1, (int64_t)list.size()));
+    if (ctx->stream) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (T.mem) (void)hipFree(T.mem);
+    T.mem = nullptr;
+    T.version = -1;
+    hipError_t e = hipMalloc(&T.mem, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        T.mem = nullptr;
+        return fail(ctx, GABI_ENOMEM, "treecode device allocation failed");
+    }
+    T.bytes = total;
+    char *base = static_cast<char *>(T.mem);
+    T.spos = reinterpret_cast<double4 *>(base + o_spos);
+    T.snrm = reinterpret_cast<double4 *>(base + o_snrm);
+    T.sw = reinterpret_cast<double4 *>(base + o_sw);
+    T.ppos = reinterpret_cast<double4 *>(base + o_ppos);
+    T.pw = reinterpret_cast<double4 *>(base + o_pw);
+    T.perm_d = reinterpret_cast<int *>(base + o_perm);
+    T.cheb = reinterpret_cast<double *>(base + o_cheb);
+    T.clusters = reinterpret_cast<int4 *>(base + o_cl);
+    T.batches = reinterpret_cast<int4 *>(base + o_bt);
+    T.list = reinterpret_cast<int4 *>(base + o_li);
+    auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream)
+                     : hipSuccess;
+    };
+    GABI_HIP(ctx, up(T.spos, spos.data(), 32 * (size_t)n));
+    GABI_HIP(ctx, up(T.snrm, snrm.data(), 32 * (size_t)n));
+    GABI_HIP(ctx, up(T.ppos, ppos.data(), 32 * ppos.size()));
+    GABI_HIP(ctx, up(T.perm_d, T.perm.data(), 4 * (size_t)n));
+    GABI_HIP(ctx, up(T.cheb, cheb.data(), 8 * cheb.size()));
+    GABI_HIP(ctx, up(T.clusters, clusters.data(), 16 * clusters.size()));
+    GABI_HIP(ctx, up(T.batches, batches.data(), 16 * batches.size()));
+    GABI_HIP(ctx, up(T.list, list.data(), 16 * list.size()));
+    GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    T.version = ctx->geom_version;
+    T.theta = o->theta;
+    T.degree = o->degree;
+    T.leaf = o->leaf_size;
+    return GABI_OK;
+}
+
+TreeDev tree_dev(const TreeState &T) {
+    TreeDev d{};
+    d.spos = T.spos;
+    d.snrm = T.snrm;
+    d.sw = T.sw;
+    d.ppos = T.ppos;
+    d.pw = T.pw;
+    d.perm = T.perm_d;
+    d.cheb = T.cheb;
+    d.clusters = T.clusters;
+    d.batches = T.batches;
+    d.list = T.list;
+    d.n = T.n;
+    d.degree = T.degree;
+    d.P = T.P;
+    for (int k = 0; k <= kTreeMaxDeg; ++k) d.bary[k] = T.bary[k];
+    return d;
+}
+
+int tree_product(gabi_ctx *ctx, const gabi_tree_opts *o, const double *u_dev, double *y_dev) {
+    int rc = tree_ensure(ctx, o);
+    if (rc) return rc;
+    const TreeState &T = *ctx->tree;
+    const TreeDev d = tree_dev(T);
+    const double eps = ctx->eps2 / ctx->eps1;
+    const PairConstF64 pc{ctx->kappa, eps, 1.0 / eps};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing) {
+        if (hipEventCreate(&e0) != hipSuccess) e0 = nullptr;
+        else if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            e0 = e1 = nullptr;
+        }
+        if (e0) (void)hipEventRecord(e0, ctx->stream);
+    }
+    hipLaunchKernelGGL(tree_prep_kernel, dim3((T.n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       ctx->stream, d, u_dev);
+    if (T.n_clusters > 0)
+        hipLaunchKernelGGL(tree_weights_kernel, dim3(T.n_clusters), dim3(kBlock), 0, ctx->stream,
+                           d);
+    hipLaunchKernelGGL(tree_eval_kernel, dim3(T.n_batches), dim3(kBlock), 0, ctx->stream, d, pc,
+                       0.5 * (1.0 + eps), 0.5 * (1.0 + 1.0 / eps), u_dev, y_dev);
+    if (e0 && e1) {
+        (void)hipEventRecord(e1, ctx->stream);
+        ctx->pending[2].push_back({e0, e1});
+    }
+    GABI_HIP(ctx, hipGetLastError());
+    return GABI_OK;
+}
+
+}  // namespace
+}  // namespace gabi
+
+using namespace gabi;
+
+extern "C" {
+
+int gabi_tree_matvec_dev(gabi_ctx *ctx, const gabi_tree_opts *opts, const double *u_dev,
+                         double *y_dev) {
+    if (!ctx) return GABI_EINVAL;
+    if (ctx->n == 0) return fail(ctx, GABI_ESTATE, "surface not set");
+    if (!ctx->params_set) return fail(ctx, GABI_ESTATE, "parameters not set");
+    if (!u_dev || !y_dev) return fail(ctx, GABI_EINVAL, "null vector");
+    GABI_HIP(ctx, hipSetDevice(ctx->device));
+    return tree_product(ctx, opts, u_dev, y_dev);
+}
+
+int gabi_tree_matvec(gabi_ctx *ctx, const gabi_tree_opts *opts, const double *u, double *y) {
+    if (!ctx) return GABI_EINVAL;
+    if (ctx->n == 0) return fail(ctx, GABI_ESTATE, "surface not set");
+    if (!ctx->params_set) return fail(ctx, GABI_ESTATE, "parameters not set");
+    if (!u || !y) return fail(ctx, GABI_EINVAL, "null vector");
+    GABI_HIP(ctx, hipSetDevice(ctx->device));
+    // the product's device vectors: the context's staging pair, allocated
+    // with the slot on first use
+    int rc = tree_io_buffers(ctx);
+    if (rc) return rc;
+    const size_t bytes = sizeof(double) * 2 * (size_t)ctx->n;
+    GABI_HIP(ctx, hipMemcpyAsync(ctx->tree_u, u, bytes, hipMemcpyHostToDevice, ctx->stream));
+    if ((rc = tree_product(ctx, opts, ctx->tree_u, ctx->tree_y))) return rc;
+    GABI_HIP(ctx, hipMemcpyAsync(y, ctx->tree_y, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GABI_OK;
+}
+
+int gabi_tree_info_get(gabi_ctx *ctx, const gabi_tree_opts *opts, gabi_tree_info *out) {
+    if (!ctx || !out) return GABI_EINVAL;
+    if (ctx->n == 0) return fail(ctx, GABI_ESTATE, "surface not set");
+    GABI_HIP(ctx, hipSetDevice(ctx->device));
+    int rc = tree_ensure(ctx, opts);
+    if (rc) return rc;
+    *out = ctx->tree->info;
+    out->device_bytes = ctx->tree->bytes;
+    return GABI_OK;
+}
+
+int gabi_tree_plan(int64_t n, const double *cx, const double *cy, const double *cz,
+                   const gabi_tree_opts *opts, gabi_tree_info *out) {
+    if (n < 1 || !cx || !cy || !cz || !out) return GABI_EINVAL;
+    std::string msg;
+    if (validate_tree_opts(opts, msg)) return GABI_EINVAL;
+    std::vector<double4> pos((size_t)n);
+    for (int64_t i = 0; i < n; ++i) pos[(size_t)i] = make_double4(cx[i], cy[i], cz[i], 0.0);
+    TreeState T;
+    std::vector<int> batch_nodes;
+    std::vector<std::vector<std::pair<int, int>>> lists;
+    plan(T, pos.data(), n, opts->theta, opts->degree, opts->leaf_size, batch_nodes, lists);
+    *out = T.info;
+    out->device_bytes = 0;
+    return GABI_OK;
+}
+
+}  // extern "C"

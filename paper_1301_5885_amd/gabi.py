@@ -41,7 +41,12 @@ EXPORTS = (
     "gabi_server_create", "gabi_server_submit", "gabi_server_poll",
     "gabi_server_drain", "gabi_server_stats_get", "gabi_server_clock",
     "gabi_server_last_error", "gabi_server_destroy", "gabi_tune_set", "gabi_tune_get",
+    "gabi_set_part_budget", "gabi_get_part_budget", "gabi_tree_matvec",
+    "gabi_tree_matvec_dev", "gabi_tree_info_get", "gabi_tree_plan",
+    "gabi_msms_counts", "gabi_msms_read", "gabi_msms_orient", "gabi_pqr_count",
+    "gabi_pqr_read", "gabi_selftest_exp_neg", "gabi_server_set_round_cap",
 )
+TIMING_TREE = 2  # gabi_kernel_time kind of the treecode products
 
 # Tuned decomposition table for gfx950, applied when the library is loaded
 # (set GABI_TUNING=none to keep the built-in defaults, or to another path).
@@ -90,6 +95,23 @@ class ResultC(C.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "info"}
         d["info"] = self.info.as_dict()
         return d
+
+
+class TreeOpts(C.Structure):
+    _fields_ = [("theta", C.c_double), ("degree", C.c_int32), ("leaf_size", C.c_int32)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "leaves", "clusters_with_proxies", "far_entries", "near_entries", "far_pairs",
+        "near_pairs", "device_bytes")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def tree_opts(theta=0.7, degree=5, leaf_size=256):
+    return TreeOpts(float(theta), int(degree), int(leaf_size))
 
 
 class ServerStats(C.Structure):
@@ -150,6 +172,23 @@ def load():
     lib.gabi_device_bytes.restype = C.c_int64
     lib.gabi_set_kernel_timing.argtypes = [ctx, C.c_int]
     lib.gabi_kernel_time.argtypes = [ctx, C.c_int, _dp, C.POINTER(C.c_int64), C.c_int]
+    lib.gabi_set_part_budget.argtypes = [_i64]
+    lib.gabi_get_part_budget.argtypes = []
+    lib.gabi_get_part_budget.restype = C.c_int64
+    lib.gabi_tree_matvec.argtypes = [ctx, C.POINTER(TreeOpts), _dp, _dp]
+    lib.gabi_tree_matvec_dev.argtypes = [ctx, C.POINTER(TreeOpts), _vp, _vp]
+    lib.gabi_tree_info_get.argtypes = [ctx, C.POINTER(TreeOpts), C.POINTER(TreeInfo)]
+    lib.gabi_tree_plan.argtypes = [_i64, _dp, _dp, _dp, C.POINTER(TreeOpts),
+                                   C.POINTER(TreeInfo)]
+    lib.gabi_msms_counts.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(_i64),
+                                     C.POINTER(_i64)]
+    lib.gabi_msms_read.argtypes = [C.c_char_p, C.c_char_p, _i64, _dp, _dp, _i64,
+                                   C.POINTER(C.c_int32)]
+    lib.gabi_msms_orient.argtypes = [_i64, _dp, _dp, _i64, C.POINTER(C.c_int32),
+                                     C.POINTER(_i64)]
+    lib.gabi_pqr_count.argtypes = [C.c_char_p, C.POINTER(_i64)]
+    lib.gabi_selftest_exp_neg.argtypes = [C.c_int, _i64, _dp, _dp]
+    lib.gabi_pqr_read.argtypes = [C.c_char_p, _i64, _dp, _dp, _dp]
     lib.gabi_tune_set.argtypes = [C.c_int] * 6
     lib.gabi_tune_get.argtypes = [C.c_int, C.c_int] + [C.POINTER(C.c_int)] * 4
     lib.gabi_solve_footprint.argtypes = [_i64, _i64, C.c_int32]
@@ -162,6 +201,7 @@ def load():
     lib.gabi_server_poll.argtypes = [_vp, C.POINTER(ResultC), C.c_int32,
                                      C.POINTER(C.c_int32)]
     lib.gabi_server_drain.argtypes = [_vp, C.c_double]
+    lib.gabi_server_set_round_cap.argtypes = [_vp, C.c_double, _i64]
     lib.gabi_server_stats_get.argtypes = [_vp, C.POINTER(ServerStats)]
     lib.gabi_server_clock.argtypes = [_vp]
     lib.gabi_server_clock.restype = C.c_double
@@ -172,7 +212,8 @@ def load():
     for name in EXPORTS:
         if name not in ("gabi_default_opts", "gabi_destroy", "gabi_last_error",
                         "gabi_device_bytes", "gabi_solve_footprint", "gabi_server_clock",
-                        "gabi_server_last_error", "gabi_server_destroy"):
+                        "gabi_server_last_error", "gabi_server_destroy",
+                        "gabi_get_part_budget"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     _apply_tuning(lib)
@@ -210,6 +251,78 @@ def tune_get(precision, bucket):
     if rc != OK:
         raise GabiError(rc, "gabi_tune_get")
     return sc.value, r.value, t.value, p.value
+
+
+def set_part_budget(nbytes):
+    """Partial-sum budget per molecule and precision, in bytes (see gabi.h)."""
+    rc = load().gabi_set_part_budget(int(nbytes))
+    if rc != OK:
+        raise GabiError(rc, "gabi_set_part_budget")
+
+
+def get_part_budget():
+    return int(load().gabi_get_part_budget())
+
+
+def read_msms(vert_path, face_path, orient=True):
+    """An MSMS triangulation: (V (nv, 3), F (nf, 3) 0-based int32, vertex
+    normals (nv, 3), number of faces rewound to counter-clockwise)."""
+    lib = load()
+    nv, nf = _i64(), _i64()
+    vp, fp = os.fsencode(vert_path), os.fsencode(face_path)
+    rc = lib.gabi_msms_counts(vp, fp, C.byref(nv), C.byref(nf))
+    if rc != OK:
+        raise GabiError(rc, f"gabi_msms_counts({vert_path}, {face_path})")
+    V = np.empty((nv.value, 3))
+    N = np.empty((nv.value, 3))
+    F = np.empty((nf.value, 3), dtype=np.int32)
+    tp = F.ctypes.data_as(C.POINTER(C.c_int32))
+    rc = lib.gabi_msms_read(vp, fp, nv.value, _p(V), _p(N), nf.value, tp)
+    if rc != OK:
+        raise GabiError(rc, f"gabi_msms_read({vert_path}, {face_path})")
+    flipped = _i64(0)
+    if orient:
+        rc = lib.gabi_msms_orient(nv.value, _p(V), _p(N), nf.value, tp, C.byref(flipped))
+        if rc != OK:
+            raise GabiError(rc, "gabi_msms_orient")
+    return V, F, N, flipped.value
+
+
+def selftest_exp_neg(t, device=0):
+    """The device's FP64 e^{-t} of the pair kernels at host values t >= 0."""
+    t = _f64(t).ravel()
+    out = np.empty_like(t)
+    rc = load().gabi_selftest_exp_neg(int(device), t.size, _p(t), _p(out))
+    if rc != OK:
+        raise GabiError(rc, "gabi_selftest_exp_neg")
+    return out
+
+
+def read_pqr(path):
+    """Atom records of a PQR file: (positions (n, 3), charges, radii)."""
+    lib = load()
+    n = _i64()
+    p = os.fsencode(path)
+    rc = lib.gabi_pqr_count(p, C.byref(n))
+    if rc != OK:
+        raise GabiError(rc, f"gabi_pqr_count({path})")
+    xyz, q, r = np.empty((n.value, 3)), np.empty(n.value), np.empty(n.value)
+    rc = lib.gabi_pqr_read(p, n.value, _p(xyz), _p(q), _p(r))
+    if rc != OK:
+        raise GabiError(rc, f"gabi_pqr_read({path})")
+    return xyz, q, r
+
+
+def tree_plan(centroids, theta=0.7, degree=5, leaf_size=256):
+    """Treecode statistics from centroids alone (host only, no device)."""
+    c = _f64(centroids).reshape(-1, 3)
+    cols = [np.ascontiguousarray(c[:, k]) for k in range(3)]
+    info = TreeInfo()
+    o = tree_opts(theta, degree, leaf_size)
+    rc = load().gabi_tree_plan(c.shape[0], *[_p(x) for x in cols], C.byref(o), C.byref(info))
+    if rc != OK:
+        raise GabiError(rc, "gabi_tree_plan")
+    return info.as_dict()
 
 
 def _f64(a):
@@ -428,6 +541,30 @@ class Context:
         self._check(self._lib.gabi_energy_dev(self._h, up, C.byref(e)), "gabi_energy_dev")
         return e.value
 
+    # -- treecode product
+    def tree_matvec(self, u, theta=0.7, degree=5, leaf_size=256):
+        o = tree_opts(theta, degree, leaf_size)
+        ua = _f64(u)
+        y = np.empty(2 * self.n)
+        self._check(self._lib.gabi_tree_matvec(self._h, C.byref(o), _p(ua), _p(y)),
+                    "gabi_tree_matvec")
+        return y
+
+    def tree_matvec_dev(self, u, y, theta=0.7, degree=5, leaf_size=256):
+        self.set_stream()
+        o = tree_opts(theta, degree, leaf_size)
+        self._check(self._lib.gabi_tree_matvec_dev(self._h, C.byref(o),
+                                                   _torch_ptr(u, 2 * self.n, "u"),
+                                                   _torch_ptr(y, 2 * self.n, "y")),
+                    "gabi_tree_matvec_dev")
+
+    def tree_info(self, theta=0.7, degree=5, leaf_size=256):
+        o = tree_opts(theta, degree, leaf_size)
+        info = TreeInfo()
+        self._check(self._lib.gabi_tree_info_get(self._h, C.byref(o), C.byref(info)),
+                    "gabi_tree_info_get")
+        return info.as_dict()
+
     # -- accounting and timing
     def device_bytes(self):
         return int(self._lib.gabi_device_bytes(self._h))
@@ -537,6 +674,12 @@ class Server:
         for r in out:
             self._keep.pop(r["ticket"], None)
         return out
+
+    def set_round_cap(self, slack, floor_elements=0):
+        """Oldest-first round cap (see include/gabi.h); slack < 0 disables."""
+        rc = self._lib.gabi_server_set_round_cap(self._h, float(slack), int(floor_elements))
+        if rc != OK:
+            raise GabiError(rc, "gabi_server_set_round_cap")
 
     def drain(self, timeout_s=600.0):
         return self._lib.gabi_server_drain(self._h, float(timeout_s)) == OK

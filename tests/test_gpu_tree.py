@@ -1,0 +1,129 @@
+"""GPU: the treecode product (barycentric Lagrange treecode, tree.hip)
+against its CPU oracle (oracle/treecode.py, the same method written
+independently) and against the direct-sum product.
+
+Tolerances: the device and the oracle build the same tree and interaction
+lists (checked exactly on the host in test_abi_cpu.py), so they compute the
+same approximation and differ only in rounding and summation order: FP64,
+normwise and max-norm <= 1e-12.  theta = 0 is the direct sum: <= 1e-13 of
+the device's direct FP64 product.  The approximation error itself (against
+the exact product) falls with degree and theta as the oracle's does.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.treecode as tc
+from paper_1301_5885_amd import gabi
+from paper_1301_5885_amd.synth import config_problem, icosphere, star_surface
+from test_gpu_parity import rel, relmax
+
+pytestmark = pytest.mark.gpu
+EPS1, EPS2, KAPPA = 1.0, 80.0, 0.1257
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def surface(name):
+    if name == "sphere_5120":
+        return icosphere(16, 10.0)
+    V, F, _ = star_surface(12, 9.0, np.random.default_rng(5))   # N = 2880
+    return V, F
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gabi.Context(0)
+    yield c
+    c.close()
+
+
+def load(ctx, V, F, kappa=KAPPA):
+    ctx.set_surface_mesh(V, F)
+    ctx.set_charges(np.zeros((1, 3)), np.ones(1))
+    ctx.set_params(EPS1, EPS2, kappa)
+    return oracle.mesh_elements(V, F)
+
+
+@pytest.mark.parametrize("theta,degree,leaf", [(0.7, 4, 64), (0.5, 6, 128), (0.8, 2, 256),
+                                               (0.9, 8, 200)])
+@pytest.mark.parametrize("name", ["sphere_5120", "star_2880"])
+def test_tree_product_matches_treecode_oracle(ctx, name, theta, degree, leaf):
+    V, F = surface(name)
+    log(f"[tree] {name} theta={theta} degree={degree} leaf={leaf}")
+    el = load(ctx, V, F)
+    u = np.random.default_rng(el.n + degree).normal(size=2 * el.n)
+    y = ctx.tree_matvec(u, theta, degree, leaf)
+    y_ref, st = tc.matvec(el, u, EPS1, EPS2, KAPPA, theta=theta, degree=degree, leaf=leaf,
+                          stats=True)
+    info = ctx.tree_info(theta, degree, leaf)
+    log(f"    {rel(y, y_ref):.2e} {info}")
+    assert info["far_entries"] == st.far_entries and info["near_pairs"] == st.near_pairs
+    assert rel(y, y_ref) <= 1e-12 and relmax(y, y_ref) <= 1e-12
+    # the approximation error against the exact product
+    y_exact = oracle.matvec(el, u, EPS1, EPS2, KAPPA)
+    log(f"    vs exact: device {rel(y, y_exact):.2e} oracle {rel(y_ref, y_exact):.2e}")
+    assert abs(rel(y, y_exact) - rel(y_ref, y_exact)) <= 1e-12
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.3])
+def test_tree_kappa_cases(ctx, kappa):
+    V, F = surface("star_2880")
+    el = load(ctx, V, F, kappa)
+    u = np.random.default_rng(7).normal(size=2 * el.n)
+    y = ctx.tree_matvec(u, 0.7, 5, 64)
+    y_ref = tc.matvec(el, u, EPS1, EPS2, kappa, theta=0.7, degree=5, leaf=64)
+    assert rel(y, y_ref) <= 1e-12
+
+
+def test_tree_theta_zero_is_the_direct_product(ctx):
+    V, F = surface("sphere_5120")
+    el = load(ctx, V, F)
+    u = np.random.default_rng(3).normal(size=2 * el.n)
+    y = ctx.tree_matvec(u, 0.0, 3, 256)
+    assert ctx.tree_info(0.0, 3, 256)["far_entries"] == 0
+    assert rel(y, ctx.matvec(u, gabi.FP64)) <= 1e-13
+
+
+def test_tree_device_entry_point_and_repeatability(ctx):
+    import torch
+    V, F = surface("star_2880")
+    el = load(ctx, V, F)
+    u = np.random.default_rng(11).normal(size=2 * el.n)
+    y_host = ctx.tree_matvec(u, 0.7, 4, 64)
+    ud = torch.tensor(u, device="cuda")
+    yd = torch.empty_like(ud)
+    ctx.tree_matvec_dev(ud, yd, 0.7, 4, 64)
+    torch.cuda.synchronize()
+    assert np.array_equal(yd.cpu().numpy(), y_host)
+    assert np.array_equal(ctx.tree_matvec(u, 0.7, 4, 64), y_host)
+
+
+def test_tree_bad_options_rejected(ctx):
+    V, F = surface("star_2880")
+    load(ctx, V, F)
+    u = np.zeros(2 * len(F))
+    for kw in (dict(theta=1.2), dict(degree=0), dict(degree=9), dict(leaf_size=300)):
+        args = dict(theta=0.5, degree=3, leaf_size=64)
+        args.update(kw)
+        with pytest.raises(gabi.GabiError):
+            ctx.tree_matvec(u, **args)
+
+
+def test_tree_full_size_against_direct(ctx):
+    """N = 81,920: the treecode product of the star workload against the
+    device's direct FP64 product (the oracle's treecode takes too long at
+    this size): an approximation error of the size the oracle shows at
+    smaller N for these options."""
+    p = config_problem("star")
+    el = load(ctx, p.V, p.F)
+    u = np.random.default_rng(2).normal(size=2 * el.n)
+    y = ctx.tree_matvec(u, 0.7, 5, 256)
+    err = rel(y, ctx.matvec(u, gabi.FP64))
+    log(f"[tree full size] N={el.n} err vs direct {err:.2e} {ctx.tree_info(0.7, 5, 256)}")
+    assert err <= 1e-5
