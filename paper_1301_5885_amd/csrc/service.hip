@@ -16,6 +16,7 @@
 // host-driven GMRES; a device-resident GMRES(m) also holds the basis
 // (m+1)*2N and the split partial sums, which gabi_solve_footprint counts.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -371,9 +372,37 @@ struct gabi_server {
     int64_t seq = 0;
     std::thread worker;
 
+    // round cap (gabi_server_set_round_cap): slack < 0 runs every active
+    // request each round
+    std::atomic<double> cap_slack{-1.0};
+    std::atomic<int64_t> cap_floor_n{0};
+
     double clock() const { return now_s() - t0; }
     void run();
+    std::vector<Slot *> capped_round(const std::vector<Slot *> &iterate) const;
 };
+
+// The requests of a round under the cap: in admission order (the active
+// list's order), the oldest always, then each one whose work keeps the
+// round's total within max((1 + slack) x the oldest's work, floor^2), where
+// a request's work is N^2 (its products' pairs).  The others wait for a
+// later round; no request's arithmetic depends on which rounds it joins.
+std::vector<Slot *> gabi_server::capped_round(const std::vector<Slot *> &iterate) const {
+    if (iterate.empty()) return iterate;
+    auto work = [](const Slot *s) { return (double)s->mol.n * (double)s->mol.n; };
+    const double floor_n = (double)cap_floor_n.load();
+    const double cap = std::max((1.0 + cap_slack.load()) * work(iterate[0]), floor_n * floor_n);
+    std::vector<Slot *> out;
+    double sum = 0.0;
+    for (Slot *s : iterate) {
+        const double w = work(s);
+        if (out.empty() || sum + w <= cap) {
+            out.push_back(s);
+            sum += w;
+        }
+    }
+    return out;
+}
 
 void gabi_server::run() {
     std::string e;
@@ -437,10 +466,12 @@ void gabi_server::run() {
             stats.max_active = std::max<int64_t>(stats.max_active, (int64_t)active.size());
             for (auto &s : active) run_list.push_back(s.get());
         }
-        // one round for every active request that still iterates
+        // one round for the active requests that still iterate: all of them,
+        // or under a round cap those that fit, oldest first
         std::vector<Slot *> iterate;
         for (Slot *s : run_list)
             if (!slot_finished(*s, opts)) iterate.push_back(s);
+        if (cap_slack >= 0.0) iterate = capped_round(iterate);
         if (rc == GABI_OK && !iterate.empty()) {
             rc = ex->round(iterate, e);
             for (Slot *s : iterate) s->rounds++;
@@ -641,6 +672,13 @@ int gabi_server_drain(gabi_server *srv, double timeout_s) {
         lk, std::chrono::duration<double>(std::max(0.0, timeout_s)),
         [&] { return srv->stats.completed >= srv->stats.submitted || srv->stop; });
     return ok && srv->stats.completed >= srv->stats.submitted ? GABI_OK : GABI_EBUSY;
+}
+
+int gabi_server_set_round_cap(gabi_server *srv, double slack, int64_t floor_elements) {
+    if (!srv || !std::isfinite(slack) || floor_elements < 0) return GABI_EINVAL;
+    srv->cap_slack.store(slack);
+    srv->cap_floor_n.store(floor_elements);
+    return GABI_OK;
 }
 
 int gabi_server_stats_get(gabi_server *srv, gabi_server_stats *out) {

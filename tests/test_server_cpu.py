@@ -143,3 +143,34 @@ def test_duplicate_tags_keep_every_request_alive_until_polled():
         assert sorted(r["ticket"] for r in got) == sorted(tickets)
         assert all(r["tag"] == 7 for r in got)
         assert s.in_flight() == []
+
+
+def test_round_cap_serves_the_oldest_first():
+    """Under a round cap the oldest active request runs every round and a
+    younger one joins a round only while the round's work stays within the
+    cap: with a tight cap a medium request submitted after a large one waits
+    for it, without a cap it finishes first (fewer rounds)."""
+    def run_pair(slack):
+        large = request(48, tag=0, seed=1)     # N = 46080: 12 mock rounds
+        medium = request(24, tag=1, seed=2)    # N = 11520: 3 mock rounds
+        with gabi.Server(device=-1, budget_bytes=1 << 34, max_slots=4,
+                         mock_round_seconds=0.01) as s:
+            if slack is not None:
+                s.set_round_cap(slack, 0)
+            s.submit(large)
+            time.sleep(0.03)
+            s.submit(medium)
+            assert s.drain(60.0)
+            res = {r["tag"]: r for r in s.poll()}
+        return res
+    free = run_pair(None)
+    assert free[1]["t_done"] < free[0]["t_done"]
+    capped = run_pair(0.01)    # 0.01 x 46080^2 < 11520^2: no room beside the large one
+    assert capped[0]["t_done"] < capped[1]["t_done"]
+    roomy = run_pair(0.1)      # 0.1 x 46080^2 > 11520^2: both share the rounds
+    assert roomy[1]["t_done"] < roomy[0]["t_done"]
+    with gabi.Server(device=-1, budget_bytes=1 << 30, max_slots=2) as s:
+        with pytest.raises(gabi.GabiError):
+            s.set_round_cap(float("nan"), 0)
+        with pytest.raises(gabi.GabiError):
+            s.set_round_cap(0.5, -1)
