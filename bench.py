@@ -360,6 +360,68 @@ def warm_sequence(ctx, gabi, p, steps):
             "max_energy_rel_diff_warm_vs_cold": max(abs(a / b - 1) for a, b in zip(ew, ec))}
 
 
+TREE_OPTS = (0.7, 5, 256)   # theta, degree, leaf size of the treecode timing
+
+
+def tree_crossover(gabi, torch, nus=(16, 32, 64, 96, 128), reps=3):
+    """Direct-sum (FP64 and FP32-pair) against treecode (FP64) products on
+    geodesic spheres of about 4 elements per square Angstrom: per-product
+    device time (HIP events on the context's stream, averaged over `reps`)
+    and the treecode's error against the direct FP64 product; the crossover
+    is the smallest N measured at which the treecode is faster than the
+    direct FP64 product."""
+    import math
+    import numpy as np
+    from paper_1301_5885_amd.synth import icosphere
+    theta, degree, leaf = TREE_OPTS
+    rows = []
+    for nu in nus:
+        n = 20 * nu * nu
+        V, F = icosphere(nu, math.sqrt(n / (16 * math.pi)))
+        with gabi.Context(0) as ctx:
+            ctx.set_surface_mesh(V, F)
+            ctx.set_charges(np.zeros((1, 3)), np.ones(1))
+            ctx.set_params(1.0, 80.0, 0.1257)
+            u = torch.tensor(np.random.default_rng(nu).normal(size=2 * n), device="cuda")
+            y = torch.empty_like(u)
+            yt = torch.empty_like(u)
+            ctx.set_stream()
+            stream = torch.cuda.current_stream()
+
+            def timed(fn):
+                fn()                                   # warm-up (builds, uploads)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / reps
+
+            t64 = timed(lambda: ctx.matvec_dev(u, y, gabi.FP64))
+            t32 = timed(lambda: ctx.matvec_dev(u, yt, gabi.FP32_PAIR))
+            t_tree = timed(lambda: ctx.tree_matvec_dev(u, yt, theta, degree, leaf))
+            info = ctx.tree_info(theta, degree, leaf)
+            ctx.matvec_dev(u, y, gabi.FP64)
+            ctx.tree_matvec_dev(u, yt, theta, degree, leaf)
+            torch.cuda.synchronize()
+            err = float(torch.linalg.norm(yt - y) / torch.linalg.norm(y))
+        rows.append({"N": n, "direct_fp64_ms": round(t64, 4), "direct_fp32_pair_ms": round(t32, 4),
+                     "tree_fp64_ms": round(t_tree, 4), "tree_rel_err_vs_direct": err,
+                     "tree_pairs_per_product": info["far_pairs"] + info["near_pairs"],
+                     "tree_device_bytes": info["device_bytes"]})
+        log(f"[bench] tree N={n}: direct {t64:.3f} ms (fp32-pair {t32:.3f}), tree {t_tree:.3f} "
+            f"ms, err {err:.2e}")
+    faster = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp64_ms"]]
+    return {"opts": {"theta": theta, "degree": degree, "leaf_size": leaf},
+            "method": "barycentric Lagrange treecode (particle-cluster, target batches), FP64",
+            "rows": rows,
+            "crossover_N_vs_fp64": faster[0] if faster else None,
+            "crossover_note": "smallest measured N with the treecode product faster than "
+                              "the direct FP64 product (None: not within the sizes measured)"}
+
+
 def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves):
     """Mixed and FP64 solves of one workload on one context."""
     from paper_1301_5885_amd.synth import config_problem
@@ -426,6 +488,8 @@ def main():
     ap.add_argument("--sequence-steps", type=int, default=8,
                     help="nearby problems solved cold and warm-started after the timing, "
                          "on the secondary workload (0: skip)")
+    ap.add_argument("--no-tree", action="store_true",
+                    help="skip the direct-sum/treecode product timing")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run one device copy of this many MiB "
                          "(a kernel of known traffic for scaling HBM counters)")
@@ -497,6 +561,9 @@ def main():
             line["warm_sequence"]["workload"] = args.secondary
             log(f"[bench] sequence: {line['warm_sequence']}")
         ctx2.close()
+    if not args.no_tree:
+        log("[bench] direct-sum vs treecode products")
+        line["treecode"] = tree_crossover(gabi, torch)
     if serve_problems is not None:
         log(f"[bench] serving {args.serve_requests} requests")
         line["serving"] = serve.run(args.serve_requests, args.serve_slots,
