@@ -260,6 +260,8 @@ def test_full_size_solves_against_golden(ctx, workload):
     (within one) and land on its energy (within 1e-9)."""
     import json
     path = os.path.join(os.path.dirname(__file__), "golden", f"{workload}_reference.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle solve for {workload} (tests/golden/make_golden.py)")
     with open(path) as f:
         ref = json.load(f)
     p = config_problem(workload)
