@@ -22,12 +22,17 @@
 //    directly when it has at most P elements), else a leaf acts directly and
 //    an inner node hands over to its children.
 //
-// Per product three kernels run: weights in tree order (tree_prep), the
-// modified weights (tree_weights, one workgroup per proxy cluster), and the
-// sums (tree_eval, one workgroup per batch, one target per thread, the
-// batch's sources staged through LDS 256 records at a time; the same pair
-// arithmetic as the direct product, FP64).  Every sum is taken in a fixed
-// order, so results are reproducible bit for bit.
+// Per product four kernels run: weights in tree order (tree_prep), the
+// modified weights (tree_weights, one workgroup per proxy cluster), the
+// sums (tree_eval) and their reduction (tree_finish).  A batch's interaction
+// list is cut into work items of a bounded number of sources, one workgroup
+// each: the item's sources are staged through LDS 256 records at a time and
+// every target of the batch is served by 256/P threads (P the batch size
+// rounded up to a power of two) that take interleaved sources, their sums
+// added in thread order; the item writes one partial per target, and
+// tree_finish adds a batch's items in list order.  The pair arithmetic is
+// the direct product's, FP64.  Every sum is taken in a fixed order, so
+// results are reproducible bit for bit.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -67,8 +72,11 @@ struct TreeState {
     int *perm_d = nullptr;
     double *cheb = nullptr;   // 3 (n+1) nodes per cluster
     int4 *clusters = nullptr;  // (begin, end, proxy offset, 0)
-    int4 *batches = nullptr;   // (begin, end, list offset, list length)
+    int4 *batches = nullptr;   // (begin, end, first item, item count)
     int4 *list = nullptr;      // (0 near | 1 far, begin, end, 0)
+    int4 *items = nullptr;     // (batch, list begin, list end, 0)
+    double2 *ipart = nullptr;  // [item][kBlock] partial (top, bot) per target
+    int n_items = 0;
 };
 
 namespace {
@@ -241,7 +249,8 @@ struct TreeDev {
     double4 *pw;
     const int *perm;
     const double *cheb;
-    const int4 *clusters, *batches, *list;
+    const int4 *clusters, *batches, *list, *items;
+    double2 *ipart;
     int n, degree, P;
     double bary[kTreeMaxDeg + 1];
 };
@@ -323,22 +332,29 @@ __global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T) {
     }
 }
 
-// The sums of one batch: its targets (one per thread) against the sources of
-// its interaction list in list order (near: elements, the target itself
-// skipped; far: proxies), then y = D u - sums at the elements' own indices.
-__global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF64 pc,
-                                                          double d_top, double d_bot,
-                                                          const double *__restrict__ u,
-                                                          double *__restrict__ y) {
+// The sums of one work item: the batch's targets against the sources of its
+// list entries [l0, l1) in list order (near: elements, the target itself
+// skipped; far: proxies).  Thread t serves target t mod P with the sources
+// j = t / P (mod G) of every staged chunk, G = 256 / P; the G sums of a
+// target are added in thread order through LDS and stored as the item's
+// partial.
+__global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF64 pc) {
     __shared__ double4 s_pos[kBlock];
     __shared__ double4 s_w[kBlock];
-    const int4 bt = T.batches[blockIdx.x];
-    const int p = bt.x + (int)threadIdx.x;
-    const bool act = p < bt.y;
+    __shared__ double2 s_sum[kBlock];
+    const int4 item = T.items[blockIdx.x];
+    const int4 bt = T.batches[item.x];
+    const int bsz = bt.y - bt.x;
+    int P = 1;
+    while (P < bsz) P <<= 1;
+    const int G = kBlock / P;
+    const int tid = (int)threadIdx.x, tg = tid % P, grp = tid / P;
+    const int p = bt.x + tg;
+    const bool act = tg < bsz;
     const int pc_ = act ? p : bt.x;
     const double4 x = T.spos[pc_], nu = T.snrm[pc_];
     double top = 0.0, bot = 0.0;
-    for (int e = bt.z; e < bt.z + bt.w; ++e) {
+    for (int e = item.y; e < item.z; ++e) {
         const int4 it = T.list[e];
         const bool far = it.x == 1;
         const double4 *src_p = far ? T.ppos : T.spos;
@@ -346,33 +362,52 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
         for (int j0 = it.y; j0 < it.z; j0 += kBlock) {
             const int cnt = min(kBlock, it.z - j0);
             __syncthreads();
-            if ((int)threadIdx.x < cnt) {
-                s_pos[threadIdx.x] = src_p[j0 + threadIdx.x];
-                s_w[threadIdx.x] = src_w[j0 + threadIdx.x];
+            if (tid < cnt) {
+                s_pos[tid] = src_p[j0 + tid];
+                s_w[tid] = src_w[j0 + tid];
             }
             __syncthreads();
             const bool self = !far && j0 < bt.y && j0 + cnt > bt.x;
-            if (!self) {
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const double4 q = s_pos[jj], w = s_w[jj];
-                    pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
-                             w.w, top, bot);
-                }
-            } else {
-                for (int jj = 0; jj < cnt; ++jj) {
-                    if (j0 + jj == p) continue;
-                    const double4 q = s_pos[jj], w = s_w[jj];
-                    pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
-                             w.w, top, bot);
-                }
+            for (int jj = grp; jj < cnt; jj += G) {
+                if (self && j0 + jj == p) continue;
+                const double4 q = s_pos[jj], w = s_w[jj];
+                pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
+                         w.w, top, bot);
             }
         }
     }
-    if (act) {
-        const int j = T.perm[p];
-        y[j] = d_top * u[j] - top;
-        y[T.n + j] = d_bot * u[T.n + j] - bot;
+    __syncthreads();
+    s_sum[tid] = make_double2(top, bot);
+    __syncthreads();
+    if (grp == 0) {
+        double2 acc = s_sum[tg];
+        for (int g = 1; g < G; ++g) {
+            const double2 v = s_sum[g * P + tg];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        T.ipart[(size_t)blockIdx.x * kBlock + tg] = acc;
     }
+}
+
+// y = D u - sums at the elements' own indices, a batch's item partials
+// added in list order.
+__global__ __launch_bounds__(kBlock) void tree_finish_kernel(TreeDev T, double d_top,
+                                                            double d_bot,
+                                                            const double *__restrict__ u,
+                                                            double *__restrict__ y) {
+    const int4 bt = T.batches[blockIdx.x];
+    const int tg = (int)threadIdx.x;
+    if (tg >= bt.y - bt.x) return;
+    double top = 0.0, bot = 0.0;
+    for (int k = bt.z; k < bt.z + bt.w; ++k) {
+        const double2 v = T.ipart[(size_t)k * kBlock + tg];
+        top += v.x;
+        bot += v.y;
+    }
+    const int j = T.perm[bt.x + tg];
+    y[j] = d_top * u[j] - top;
+    y[T.n + j] = d_bot * u[T.n + j] - bot;
 }
 
 // ------------------------------------------------------------------ host
@@ -444,18 +479,40 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
                 make_double4(cn[k1], cn[np1 + k2], cn[2 * np1 + k3], 0.0);
         }
     }
-    std::vector<int4> batches(batch_nodes.size()), list;
-    for (size_t b = 0; b < batch_nodes.size(); ++b) {
-        const TreeNode &B = T.nodes[(size_t)batch_nodes[b]];
-        batches[b] = make_int4(B.begin, B.end, (int)list.size(), (int)lists[b].size());
+    std::vector<int4> batches(batch_nodes.size()), list, items;
+    int64_t total_src = 0;
+    for (size_t b = 0; b < batch_nodes.size(); ++b)
         for (auto &kn : lists[b]) {
             const TreeNode &C = T.nodes[(size_t)kn.second];
+            total_src += kn.first == 1 ? T.P : (C.end - C.begin);
+        }
+    // sources per work item: enough items to fill the device several times
+    // over, each item at least a few LDS stages
+    const int64_t item_src = std::min<int64_t>(
+        32768, std::max<int64_t>(1024, total_src / 8192 / 256 * 256));
+    for (size_t b = 0; b < batch_nodes.size(); ++b) {
+        const TreeNode &B = T.nodes[(size_t)batch_nodes[b]];
+        const int first_item = (int)items.size();
+        int l0 = (int)list.size();
+        int64_t acc = 0;
+        for (auto &kn : lists[b]) {
+            const TreeNode &C = T.nodes[(size_t)kn.second];
+            const int64_t cnt = kn.first == 1 ? T.P : (C.end - C.begin);
+            if (acc > 0 && acc + cnt > item_src) {  // close the item before this entry
+                items.push_back(make_int4((int)b, l0, (int)list.size(), 0));
+                l0 = (int)list.size();
+                acc = 0;
+            }
             if (kn.first == 1)
                 list.push_back(make_int4(1, C.proxy * T.P, C.proxy * T.P + T.P, 0));
             else
                 list.push_back(make_int4(0, C.begin, C.end, 0));
+            acc += cnt;
         }
+        items.push_back(make_int4((int)b, l0, (int)list.size(), 0));
+        batches[b] = make_int4(B.begin, B.end, first_item, (int)items.size() - first_item);
     }
+    T.n_items = (int)items.size();
     // one device block
     auto al = [](int64_t v) { return (v + 255) & ~int64_t(255); };
     const int64_t o_spos = 0;
@@ -468,7 +525,9 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     const int64_t o_cl = al(o_cheb + 8 * std::max<int64_t>(1, (int64_t)cheb.size()));
     const int64_t o_bt = al(o_cl + 16 * std::max<int64_t>(1, (int64_t)nc));
     const int64_t o_li = al(o_bt + 16 * (int64_t)batches.size());
-    const int64_t total = al(o_li + 16 * std::max<int64_t>(1, (int64_t)list.size()));
+    const int64_t o_it = al(o_li + 16 * std::max<int64_t>(1, (int64_t)list.size()));
+    const int64_t o_ip = al(o_it + 16 * (int64_t)items.size());
+    const int64_t total = al(o_ip + 16 * (int64_t)kBlock * (int64_t)items.size());
     if (ctx->stream) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (T.mem) (void)hipFree(T.mem);
     T.mem = nullptr;
@@ -491,6 +550,8 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     T.clusters = reinterpret_cast<int4 *>(base + o_cl);
     T.batches = reinterpret_cast<int4 *>(base + o_bt);
     T.list = reinterpret_cast<int4 *>(base + o_li);
+    T.items = reinterpret_cast<int4 *>(base + o_it);
+    T.ipart = reinterpret_cast<double2 *>(base + o_ip);
     auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream)
                      : hipSuccess;
@@ -503,6 +564,7 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     GABI_HIP(ctx, up(T.clusters, clusters.data(), 16 * clusters.size()));
     GABI_HIP(ctx, up(T.batches, batches.data(), 16 * batches.size()));
     GABI_HIP(ctx, up(T.list, list.data(), 16 * list.size()));
+    GABI_HIP(ctx, up(T.items, items.data(), 16 * items.size()));
     GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
     T.version = ctx->geom_version;
     T.theta = o->theta;
@@ -523,6 +585,8 @@ TreeDev tree_dev(const TreeState &T) {
     d.clusters = T.clusters;
     d.batches = T.batches;
     d.list = T.list;
+    d.items = T.items;
+    d.ipart = T.ipart;
     d.n = T.n;
     d.degree = T.degree;
     d.P = T.P;
@@ -551,7 +615,8 @@ int tree_product(gabi_ctx *ctx, const gabi_tree_opts *o, const double *u_dev, do
     if (T.n_clusters > 0)
         hipLaunchKernelGGL(tree_weights_kernel, dim3(T.n_clusters), dim3(kBlock), 0, ctx->stream,
                            d);
-    hipLaunchKernelGGL(tree_eval_kernel, dim3(T.n_batches), dim3(kBlock), 0, ctx->stream, d, pc,
+    hipLaunchKernelGGL(tree_eval_kernel, dim3(T.n_items), dim3(kBlock), 0, ctx->stream, d, pc);
+    hipLaunchKernelGGL(tree_finish_kernel, dim3(T.n_batches), dim3(kBlock), 0, ctx->stream, d,
                        0.5 * (1.0 + eps), 0.5 * (1.0 + 1.0 / eps), u_dev, y_dev);
     if (e0 && e1) {
         (void)hipEventRecord(e1, ctx->stream);
