@@ -33,11 +33,12 @@ namespace gabi {
 // 2.1e-16 before rounding), then an exponent add.  Measured against a
 // 64-bit-mantissa exponential over t in [0, 60]: at most 3 ulp, 1 ulp on
 // average (the degree-12 Taylor form with a one-constant reduction it
-// replaces: 18 ulp at most, one multiply-add more).  t is clamped to 745 so
-// the exponent stays in range; e^{-745} underflows to (sub)normal zero.
+// replaces: 18 ulp at most, one multiply-add more).  t is clamped to 746 so
+// the exponent stays in range: e^{-t} < 2^-1075 for t > 745.14, which rounds
+// to zero, and 2^k e^f at t = 746 (k = -1076) does.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double exp_neg_f64(double t) {
-    t = fmin(t, 745.0);
+    t = fmin(t, 746.0);
     const double x = -t;
     const double kf = __builtin_rint(x * 1.4426950408889634074);  // x / ln2
     double f = __builtin_fma(-kf, 0x1.62e42fefa39efp-1, x);        // ln 2, rounded
