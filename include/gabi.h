@@ -177,6 +177,29 @@ int gabi_matvec(gabi_ctx *ctx, int precision, const double *u, double *y);
 int gabi_matvec_dev(gabi_ctx *ctx, int precision, const double *u_dev,
                     double *y_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * product of gabi_matvec_dev, y = A u, with no allocation of any kind.
+ * The element data come from the caller's device array elem_dev (32-byte
+ * aligned, 8 n doubles): n records (cx, cy, cz, area), then n records
+ * (nx, ny, nz, 0) of unit outward normals; it is not validated (the caller
+ * vouches for distinct centroids and unit normals).  eps1, eps2, kappa are
+ * the context's (gabi_set_params); the context's surface, slot and batch
+ * are not used.  u_dev, y_dev: 2n doubles each, device memory.  Work goes
+ * on the context's stream; the call returns once it is enqueued.  Weights,
+ * partial sums, lists and counters live in a 32 MiB library-owned device
+ * array per GPU (held until the process ends), so 1 <= n <= 65,536
+ * (GABI_EINVAL otherwise); every call rewrites it from the start.  Calls on
+ * one GPU share that array: calls that overlap in time on one GPU (other
+ * streams, other contexts, other threads) race and give wrong results.
+ * Errors: GABI_ESTATE (no parameters), GABI_EINVAL (size, null or
+ * misaligned pointer), GABI_EDEVICE.  Results equal gabi_matvec_dev's at
+ * GABI_FP64 up to the grouping of partial sums: bit for bit where the
+ * context takes the symmetric scheme in one pass (n <= 20,480 with the
+ * shipped tuning table and the default partial-sum budget).               */
+int gabi_matvec_noalloc(gabi_ctx *ctx, int64_t n, const double *elem_dev,
+                        const double *u_dev, double *y_dev);
+
 /* Solve A u = b with b from gabi_rhs.  opts may be null (defaults).  x0
  * (length 2N) is the initial guess, null for zero (Section 2.4).  u receives
  * the solution (length 2N); info may be null.  Returns GABI_OK,

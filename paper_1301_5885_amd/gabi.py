@@ -45,6 +45,7 @@ EXPORTS = (
     "gabi_tree_matvec_dev", "gabi_tree_info_get", "gabi_tree_plan",
     "gabi_msms_counts", "gabi_msms_read", "gabi_msms_orient", "gabi_pqr_count",
     "gabi_pqr_read", "gabi_selftest_exp_neg", "gabi_server_set_round_cap",
+    "gabi_matvec_noalloc",
 )
 TIMING_TREE = 2  # gabi_kernel_time kind of the treecode products
 
@@ -163,6 +164,7 @@ def load():
     lib.gabi_rhs_dev.argtypes = [ctx, _vp]
     lib.gabi_matvec.argtypes = [ctx, C.c_int, _dp, _dp]
     lib.gabi_matvec_dev.argtypes = [ctx, C.c_int, _vp, _vp]
+    lib.gabi_matvec_noalloc.argtypes = [ctx, _i64, _vp, _vp, _vp]
     lib.gabi_solve.argtypes = [ctx, C.POINTER(SolveOpts), _dp, _dp, C.POINTER(SolveInfo)]
     lib.gabi_solve_dev.argtypes = [ctx, C.POINTER(SolveOpts), _vp, _vp, C.POINTER(SolveInfo)]
     lib.gabi_energy.argtypes = [ctx, _dp, _dp]
@@ -523,6 +525,16 @@ class Context:
         self._check(self._lib.gabi_matvec_dev(
             self._h, int(precision), _torch_ptr(u, 2 * self.n, "u"),
             _torch_ptr(y, 2 * self.n, "y")), "gabi_matvec_dev")
+
+    def matvec_noalloc(self, elem, u, y):
+        """FP64 product through the allocation-free entry point: elem is a
+        contiguous float64 device tensor of 8 n values ((cx, cy, cz, area)
+        per element, then (nx, ny, nz, 0) per element); u, y of 2 n."""
+        n = elem.numel() // 8
+        self.set_stream()
+        self._check(self._lib.gabi_matvec_noalloc(
+            self._h, n, _torch_ptr(elem, 8 * n, "elem"), _torch_ptr(u, 2 * n, "u"),
+            _torch_ptr(y, 2 * n, "y")), "gabi_matvec_noalloc")
 
     def solve_dev(self, u, x0=None, **opts):
         self.set_stream()
