@@ -22,6 +22,12 @@ constexpr int kTile = 256;           // sources staged in LDS per tile
 constexpr int kPiece = 64;           // sources of one tail split
 constexpr int kBlasBlocksMax = 256;  // workgroups per molecule in reductions
 constexpr int kMaxRestart = 64;
+// Tile queues of the product: per precision a block of kCountersPerPrecision
+// ints, [0, 3) one per pair-kernel variant, [kXcdCounters, +kXcdLists) the
+// symmetric kernel's per-list queues (one list per XCD).
+constexpr int kXcdLists = 8;
+constexpr int kXcdCounters = 8;
+constexpr int kCountersPerPrecision = 16;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kCoulomb = 332.0716;  // kcal A / (mol e^2)
 
@@ -191,8 +197,11 @@ struct Batch {
     // of the symmetric group (the molecules' passes p run in one launch)
     int n_pass64 = 1, n_pass32 = 1;
     int sym_off64[kMaxPasses + 1] = {0}, sym_off32[kMaxPasses + 1] = {0};
+    // per pass, kXcdLists + 1 offsets (relative to the pass's first tile)
+    // cutting its tiles into the symmetric kernel's lists
+    int *d_xoff64 = nullptr, *d_xoff32 = nullptr;
     int4 *d_rx = nullptr;     int n_rx = 0;     // (mol, charge block, split, 0)
-    int *d_counter = nullptr;  // tile queues of the persistent product (4)
+    int *d_counter = nullptr;  // tile queues (2 x kCountersPerPrecision)
     KrylovStatus *d_status = nullptr;  // gathered statuses, one per molecule
     KrylovStatus *h_status = nullptr;  // their pinned host mirror (in h_pinned)
     void *h_pinned = nullptr;          // staging for uploads, same layout as d_mem

@@ -441,21 +441,63 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int slot,
     }
 }
 
+// The tiles of one pass come as kXcdLists lists, list x = tiles
+// [xoff[x], xoff[x+1]), each a contiguous range of row blocks (the host
+// sorts a pass by block I and cuts it into lists of equal cost), so that
+// the tiles a list's workgroups run at the same time share their blocks in
+// one L2.  Workgroups are placed on the XCDs in turn (id mod 8), and list x
+// is drained by the C workgroups with id mod 8 = x (its home workgroups,
+// local index k = id / 8) in the three phases of next_tile: entry k first
+// (no atomic), then entries C .. Q - 1 from the list's counter, Q = the
+// list's length less its length mod C, and the last partial round, entry
+// Q + k, by local index, which spreads it over the XCD's CUs.  A workgroup
+// whose home list is done helps the other lists, in turn, with their
+// counter phases.  Every entry of every list is taken exactly once, and a
+// tile's sums go to its own slot, so the order in which tiles run does not
+// change any result.  A non-persistent launch has one workgroup per tile
+// (xoff unused).
 // The FP32-pair variant is held to 8 waves per SIMD (at most 64 VGPRs).
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
     const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
-    int *__restrict__ counter, int persistent, int skip) {
+    const int *__restrict__ xoff, int *__restrict__ xcnt, int persistent, int skip) {
     using T4 = typename PairView<MIXED>::T4;
     // two 4-vectors per element of block J, each chunk stored twice; the
     // first copies also take the column sums (2 x 4 waves x 64 per chunk)
     __shared__ T4 s_stage[4 * kTile];
     __shared__ int s_next;
-    for (int t = (int)blockIdx.x; t < ntiles;
-         t = next_tile(persistent, t, ntiles, counter, &s_next)) {
+    auto run = [&](int t) {
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
         if (!(skip && load_done(M.st))) sym_tile<MIXED>(M, tile.y, tile.z, tile.w & 0xffff, s_stage);
+    };
+    if (!persistent) {
+        if ((int)blockIdx.x < ntiles) run((int)blockIdx.x);
+        return;
+    }
+    const int G = (int)gridDim.x;
+    const int home = (int)blockIdx.x % kXcdLists, k = (int)blockIdx.x / kXcdLists;
+#pragma unroll 1
+    for (int l = 0; l < kXcdLists; ++l) {
+        const int x = (home + l) % kXcdLists;
+        const int a = xoff[x], len = xoff[x + 1] - a;
+        const int C = (G - x + kXcdLists - 1) / kXcdLists;  // home workgroups of list x
+        const int Q = C > 0 && len > C ? len - len % C : len;  // end of the counter phase
+        if (l == 0 && k < len) run(a + k);
+#pragma unroll 1
+        for (;;) {
+            if (Q <= C) break;  // no counter phase
+            __syncthreads();    // the previous tile is done with LDS and s_next
+            if (threadIdx.x == 0) s_next = C + atomicAdd(&xcnt[x], 1);
+            __syncthreads();
+            const int u = s_next;
+            if (u >= Q) break;
+            run(a + u);
+        }
+        if (l == 0 && Q + k < len && Q >= C) {
+            __syncthreads();  // the previous tile is done with LDS
+            run(a + Q + k);
+        }
     }
 }
 
@@ -474,7 +516,7 @@ constexpr int kFinishQ = 4;
 constexpr int kPairVariants = 3;  // split R = 2, split R = 1, symmetric
 
 // The finish also rearms the tile queues of the product it completes: the
-// pair launches of this precision start from a zero counter, and only the
+// pair launches of this precision start from zero counters, and only the
 // finish that follows them reads or writes those counters in between.
 // st += slot 2p, sb += slot 2p + 1 of element i for p = p0 .. p1 - 1, added
 // in slot order.  The reads of eight slots are issued before their sums, so
@@ -510,6 +552,7 @@ __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
     __shared__ double acc[2][kFinishQ - 1][kBlock];
     __shared__ double lds[kBlock * kFinishQ / 64];
     if (blockIdx.x == 0 && threadIdx.x < kPairVariants) counters[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kXcdLists) counters[kXcdCounters + threadIdx.x] = 0;
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
     if (skip && load_done(M.st)) return;
@@ -574,13 +617,13 @@ __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
 // ------------------------------------------------------------------ fold
 // After pass `pass` of a symmetric product taken in several passes (not its
 // last): acc = (acc of the earlier passes, if any) + the pass's slots, added
-// as the finish adds them.  Also rearms the symmetric tile queue of this
+// as the finish adds them.  Also rearms the symmetric tile queues of this
 // precision for the next pass's launch.
 __global__ __launch_bounds__(kBlock * kFinishQ) void fold_kernel(
     const Mol *__restrict__ mols, const int2 *__restrict__ list, int precision, int pass,
     int skip, int *__restrict__ counters) {
     __shared__ double accs[2][kFinishQ - 1][kBlock];
-    if (blockIdx.x == 0 && threadIdx.x == 0) counters[2] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kXcdLists) counters[kXcdCounters + threadIdx.x] = 0;
     const int2 e = list[blockIdx.x];
     const Mol &M = mols[e.x];
     if (skip && load_done(M.st)) return;
@@ -645,17 +688,18 @@ void launch_prep(const Batch &b, hipStream_t s, int precision, int mode, int j, 
     }
 }
 
-// R = 2 or 1: split scheme with R rows per thread; R = 0: symmetric scheme
+// R = 2 or 1: split scheme with R rows per thread, one queue (counter);
+// R = 0: symmetric scheme, lists xoff[0..8] with queues counter[0..7]
 template <bool MIXED, int R>
 static void pair_group(Batch &b, hipStream_t s, const int4 *tiles, int ntiles, int *counter,
-                       int grid_cap, bool skip) {
+                       int grid_cap, bool skip, const int *xoff = nullptr) {
     if (ntiles == 0) return;
-    // the counter is zero: set by the batch upload, rearmed by every finish
-    // (and, for the symmetric queue, by the fold between passes)
+    // the counters are zero: set by the batch upload, rearmed by every finish
+    // (and, for the symmetric queues, by the fold between passes)
     const int grid = b.persistent ? std::min(ntiles, grid_cap) : ntiles;
     if constexpr (R == 0)
         hipLaunchKernelGGL((sym_pair_kernel<MIXED>), dim3(grid), dim3(kBlock), 0, s, b.d_mols,
-                           tiles, ntiles, counter, (int)b.persistent, (int)skip);
+                           tiles, ntiles, xoff, counter, (int)b.persistent, (int)skip);
     else
         hipLaunchKernelGGL((pair_kernel<MIXED, R>), dim3(grid), dim3(kBlock), 0, s, b.d_mols,
                            tiles, ntiles, counter, (int)b.persistent, (int)skip);
@@ -697,7 +741,7 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
             record_event(e0, s);
         }
     }
-    int *c = b.d_counter + (mixed ? 4 : 0);
+    int *c = b.d_counter + (mixed ? kCountersPerPrecision : 0);
     const int4 *t1 = tiles + cnt[0], *t2 = t1 + cnt[1];
     if (mixed) {
         pair_group<true, 2>(b, s, tiles, cnt[0], c, b.grid32[0], skip);
@@ -709,13 +753,15 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
     // symmetric tiles pass by pass, each pass but the last folded into the
     // accumulator before the next reuses the slots
     const int *off = mixed ? b.sym_off32 : b.sym_off64;
+    const int *xoff = mixed ? b.d_xoff32 : b.d_xoff64;
     const int passes = mixed ? b.n_pass32 : b.n_pass64;
     for (int p = 0; p < passes; ++p) {
         const int a = off[p], z = off[p + 1];
+        const int *xo = xoff + (size_t)p * (kXcdLists + 1);
         if (mixed)
-            pair_group<true, 0>(b, s, t2 + a, z - a, c + 2, b.grid32[2], skip);
+            pair_group<true, 0>(b, s, t2 + a, z - a, c + kXcdCounters, b.grid32[2], skip, xo);
         else
-            pair_group<false, 0>(b, s, t2 + a, z - a, c + 2, b.grid64[2], skip);
+            pair_group<false, 0>(b, s, t2 + a, z - a, c + kXcdCounters, b.grid64[2], skip, xo);
         if (p + 1 < passes) launch_fold(b, s, precision, p, skip);
     }
     if (e0 && e1) {
@@ -726,7 +772,7 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
 
 void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip) {
     const dim3 g(b.n_blas), blk(kBlock * kFinishQ);
-    int *c = b.d_counter + (precision == GABI_FP64 ? 0 : 4);
+    int *c = b.d_counter + (precision == GABI_FP64 ? 0 : kCountersPerPrecision);
     if (mode == kFinishDot)
         hipLaunchKernelGGL(finish_kernel<kFinishDot>, g, blk, 0, s, b.d_mols, b.d_blas,
                            precision, j, (int)skip, c);
@@ -739,7 +785,7 @@ void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j
 }
 
 void launch_fold(const Batch &b, hipStream_t s, int precision, int pass, bool skip) {
-    int *c = b.d_counter + (precision == GABI_FP64 ? 0 : 4);
+    int *c = b.d_counter + (precision == GABI_FP64 ? 0 : kCountersPerPrecision);
     hipLaunchKernelGGL(fold_kernel, dim3(b.n_blas), dim3(kBlock * kFinishQ), 0, s, b.d_mols,
                        b.d_blas, precision, pass, (int)skip, c);
 }

@@ -62,8 +62,8 @@ int scratch_address(int device, char **out, std::string &msg) {
 
 // Byte offsets of the scratch parts for n elements, and the pass structure.
 struct NoallocPlan {
-    int64_t o_mol = 0, o_elem = 0, o_blas = 0, o_tiles = 0, o_cnt = 0, o_wgt = 0, o_acc = 0,
-            o_part = 0, total = 0;
+    int64_t o_mol = 0, o_elem = 0, o_blas = 0, o_tiles = 0, o_xoff = 0, o_cnt = 0, o_wgt = 0,
+            o_acc = 0, o_part = 0, total = 0;
     int nbk = 0, n_elem = 0, n_blas = 0, ntiles = 0, slots = 0, passes = 0, last = 0;
 };
 
@@ -97,6 +97,7 @@ NoallocPlan noalloc_plan(int64_t n) {
     P.o_elem = take(sizeof(int2) * (int64_t)P.n_elem);
     P.o_blas = take(sizeof(int2) * (int64_t)P.n_blas);
     P.o_tiles = take(sizeof(int4) * (int64_t)P.ntiles);
+    P.o_xoff = take(sizeof(int) * (int64_t)(kXcdLists + 1) * P.nbk);  // passes <= nbk
     P.o_cnt = take(256);
     P.o_wgt = take(sizeof(double4) * n);
     P.o_acc = take(sizeof(double) * 2 * n);
@@ -114,14 +115,22 @@ NoallocPlan noalloc_plan(int64_t n) {
 
 // Writes the descriptor, the element and reduction block lists, the
 // symmetric tiles of every round (round order; round r writes slot r mod S
-// in pass r / S) and zero tile-queue counters into the scratch.
+// in pass r / S), the cut of each pass into the symmetric kernel's lists
+// (equal counts, in round order) and zero tile-queue counters into the
+// scratch.
 __global__ __launch_bounds__(kBlock) void noalloc_setup_kernel(Mol M, char *base, NoallocPlan P) {
     const int g = (int)(blockIdx.x * kBlock + threadIdx.x);
+    const int nbk = P.nbk;
     if (g == 0) *reinterpret_cast<Mol *>(base + P.o_mol) = M;
     if (g < 64) reinterpret_cast<int *>(base + P.o_cnt)[g] = 0;
     if (g < P.n_elem) reinterpret_cast<int2 *>(base + P.o_elem)[g] = make_int2(0, g);
     if (g < P.n_blas) reinterpret_cast<int2 *>(base + P.o_blas)[g] = make_int2(0, g);
-    const int nbk = P.nbk;
+    if (g < P.passes * (kXcdLists + 1)) {
+        const int p = g / (kXcdLists + 1), x = g % (kXcdLists + 1);
+        const int r0 = p * P.slots, r1 = min(r0 + P.slots, nbk);
+        const int len = (r1 == nbk ? P.ntiles : round_first(nbk, r1)) - round_first(nbk, r0);
+        reinterpret_cast<int *>(base + P.o_xoff)[g] = len * x / kXcdLists;
+    }
     if (g >= nbk * nbk) return;
     const int r = g / nbk, k = g % nbk;
     if (k >= round_tiles(nbk, r)) return;
@@ -207,6 +216,7 @@ int gabi_matvec_noalloc(gabi_ctx *ctx, int64_t n, const double *elem_dev, const 
     b.d_blas = reinterpret_cast<int2 *>(base + P.o_blas);
     b.n_blas = P.n_blas;
     b.d_tiles64 = reinterpret_cast<int4 *>(base + P.o_tiles);
+    b.d_xoff64 = reinterpret_cast<int *>(base + P.o_xoff);
     b.n_tiles64[2] = P.ntiles;
     b.n_pass64 = P.passes;
     for (int p = 0; p <= P.passes; ++p) {
@@ -216,7 +226,8 @@ int gabi_matvec_noalloc(gabi_ctx *ctx, int64_t n, const double *elem_dev, const 
     b.d_counter = reinterpret_cast<int *>(base + P.o_cnt);
     b.persistent = true;
     pair_grids(b.grid64, b.grid32);
-    const int setup_threads = std::max(P.nbk * P.nbk, std::max(P.n_elem, std::max(P.n_blas, 64)));
+    const int setup_threads =
+        std::max({P.nbk * P.nbk, P.n_elem, P.n_blas, 64, P.passes * (kXcdLists + 1)});
     hipLaunchKernelGGL(noalloc_setup_kernel, dim3((setup_threads + kBlock - 1) / kBlock),
                        dim3(kBlock), 0, ctx->stream, M, base, P);
     launch_prep(b, ctx->stream, GABI_FP64, kPrepU, 0, false);

@@ -376,6 +376,51 @@ void pair_grids(int g64[3], int g32[3]) {
     }
 }
 
+namespace {
+
+// The symmetric kernel's lists (see sym_pair_kernel): the tiles of each pass
+// (entries [pass_off[p], pass_off[p+1]) of `sym`) are ordered by molecule,
+// then by squares of kSquare x kSquare block pairs (I / kSquare, J / kSquare),
+// then (I, J), and cut into kXcdLists lists of about equal cost (an
+// off-diagonal tile costs two diagonal ones), each list's diagonal tiles
+// moved to its end so that its last tiles are short ones.  The tiles an
+// XCD runs at one time then come from a few squares, which touch few blocks
+// (2 kSquare per square), so their element records stay in that XCD's L2.
+// xoff receives kXcdLists + 1 offsets per pass, relative to the pass's
+// first tile.
+constexpr int kSquare = 16;
+
+void xcd_lists(int4 *sym, const std::vector<int> &pass_off, std::vector<int> &xoff) {
+    const int np = std::max<int>(1, (int)pass_off.size() - 1);
+    xoff.assign((size_t)np * (kXcdLists + 1), 0);
+    for (int p = 0; p + 1 < (int)pass_off.size(); ++p) {
+        int4 *a = sym + pass_off[p];
+        const int n = pass_off[p + 1] - pass_off[p];
+        std::stable_sort(a, a + n, [](const int4 &u, const int4 &v) {
+            if (u.x != v.x) return u.x < v.x;
+            if (u.y / kSquare != v.y / kSquare) return u.y / kSquare < v.y / kSquare;
+            if (u.z / kSquare != v.z / kSquare) return u.z / kSquare < v.z / kSquare;
+            if (u.y != v.y) return u.y < v.y;
+            return u.z < v.z;
+        });
+        int64_t total = 0;
+        for (int t = 0; t < n; ++t) total += a[t].y == a[t].z ? 1 : 2;
+        int *xo = xoff.data() + (size_t)p * (kXcdLists + 1);
+        int64_t acc = 0;
+        int x = 1;
+        for (int t = 0; t < n && x < kXcdLists; ++t) {
+            acc += a[t].y == a[t].z ? 1 : 2;
+            while (x < kXcdLists && acc * kXcdLists >= total * x) xo[x++] = t + 1;
+        }
+        for (; x <= kXcdLists; ++x) xo[x] = n;
+        for (int l = 0; l < kXcdLists; ++l)
+            std::stable_partition(a + xo[l], a + xo[l + 1],
+                                  [](const int4 &u) { return u.y != u.z; });
+    }
+}
+
+}  // namespace
+
 int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     const int nm = (int)b.slots.size();
     std::vector<Mol> mols((size_t)nm);
@@ -486,6 +531,9 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     std::vector<int> off64, off32;
     group(t64, false, c64, off64);
     group(t32, true, c32, off32);
+    std::vector<int> xoff64, xoff32;
+    xcd_lists(t64.data() + c64[0] + c64[1], off64, xoff64);
+    xcd_lists(t32.data() + c32[0] + c32[1], off32, xoff32);
 
     auto al = [](int64_t v) { return (v + 255) & ~int64_t(255); };
     const int64_t o_mols = 0;
@@ -493,7 +541,9 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     const int64_t o_blas = al(o_elem + (int64_t)sizeof(int2) * std::max<size_t>(1, elem.size()));
     const int64_t o_t64 = al(o_blas + (int64_t)sizeof(int2) * std::max<size_t>(1, blas.size()));
     const int64_t o_t32 = al(o_t64 + (int64_t)sizeof(int4) * std::max<size_t>(1, t64.size()));
-    const int64_t o_rx = al(o_t32 + (int64_t)sizeof(int4) * std::max<size_t>(1, t32.size()));
+    const int64_t o_x64 = al(o_t32 + (int64_t)sizeof(int4) * std::max<size_t>(1, t32.size()));
+    const int64_t o_x32 = al(o_x64 + (int64_t)sizeof(int) * xoff64.size());
+    const int64_t o_rx = al(o_x32 + (int64_t)sizeof(int) * xoff32.size());
     const int64_t o_cnt = al(o_rx + (int64_t)sizeof(int4) * std::max<size_t>(1, rx.size()));
     const int64_t o_st = al(o_cnt + 256);
     const int64_t total = al(o_st + (int64_t)sizeof(KrylovStatus) * std::max(1, nm));
@@ -530,6 +580,8 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     b.d_blas = reinterpret_cast<int2 *>(base + o_blas);
     b.d_tiles64 = reinterpret_cast<int4 *>(base + o_t64);
     b.d_tiles32 = reinterpret_cast<int4 *>(base + o_t32);
+    b.d_xoff64 = reinterpret_cast<int *>(base + o_x64);
+    b.d_xoff32 = reinterpret_cast<int *>(base + o_x32);
     b.d_rx = reinterpret_cast<int4 *>(base + o_rx);
     b.d_counter = reinterpret_cast<int *>(base + o_cnt);
     b.d_status = reinterpret_cast<KrylovStatus *>(base + o_st);
@@ -555,6 +607,8 @@ int batch_build(Batch &b, hipStream_t stream, std::string &err) {
     if (!blas.empty()) std::memcpy(h + o_blas, blas.data(), sizeof(int2) * blas.size());
     if (!t64.empty()) std::memcpy(h + o_t64, t64.data(), sizeof(int4) * t64.size());
     if (!t32.empty()) std::memcpy(h + o_t32, t32.data(), sizeof(int4) * t32.size());
+    std::memcpy(h + o_x64, xoff64.data(), sizeof(int) * xoff64.size());
+    std::memcpy(h + o_x32, xoff32.data(), sizeof(int) * xoff32.size());
     if (!rx.empty()) std::memcpy(h + o_rx, rx.data(), sizeof(int4) * rx.size());
     hipError_t e = hipMemcpyAsync(b.d_mem, h, (size_t)total, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
