@@ -98,12 +98,15 @@ def fifo_latencies(arrivals, service):
     return np.array(lat)
 
 
-def served(reqs, gabi, arrivals, mode, tol, budget, max_slots):
+def served(reqs, gabi, arrivals, mode, tol, budget, max_slots, cap=None):
     """Live run of the serving loop; returns latencies, energies (by tag),
-    makespan and server statistics."""
+    makespan and server statistics.  cap: (slack, floor_elements) of the
+    round cap (gabi_server_set_round_cap), or None for none."""
     results = {}
     with gabi.Server(device=0, budget_bytes=budget, max_slots=max_slots, tol=tol,
                      mode=mode) as s:
+        if cap is not None:
+            s.set_round_cap(cap[0], cap[1])
         t0 = s.clock()
         order = np.argsort(arrivals, kind="stable")
         for k in order:
@@ -145,8 +148,28 @@ def served(reqs, gabi, arrivals, mode, tol, budget, max_slots):
     return lat, energies, makespan, st
 
 
-def run(count=64, max_slots=32, budget_gib=16.0, tol=TOL, workers=16, problems=None):
-    """The whole serving comparison; returns a JSON-ready dict."""
+def parse_caps(text):
+    """'none,0.1:20480' -> [None, (0.1, 20480)]."""
+    out = []
+    for item in text.split(","):
+        item = item.strip()
+        if item in ("", "none"):
+            out.append(None)
+        else:
+            slack, floor = item.split(":")
+            out.append((float(slack), int(floor)))
+    return out
+
+
+def cap_name(cap):
+    return "none" if cap is None else f"slack {cap[0]:g}, floor {cap[1]}"
+
+
+def run(count=64, max_slots=32, budget_gib=16.0, tol=TOL, workers=16, problems=None,
+        caps=(None,)):
+    """The whole serving comparison; returns a JSON-ready dict.  The served
+    runs are repeated for every round cap in `caps`; the first is reported as
+    served_mixed, all of them under cap_sweep."""
     t_gen = time.perf_counter()
     if problems is None:
         problems = make_problems(count, workers)
@@ -180,15 +203,20 @@ def run(count=64, max_slots=32, budget_gib=16.0, tol=TOL, workers=16, problems=N
     arrivals = np.cumsum(gaps) - gaps[0]
     out["arrival_rate_per_s"] = round(rate, 4)
 
-    log(f"[serve] served mixed, Poisson arrivals at {rate:.2f}/s")
-    lat_p, e_sv, span_p, st_p = served(reqs, gabi, arrivals, gabi.SOLVE_MIXED_IR, tol, budget,
-                                       max_slots)
-    log(f"[serve]   p50 {1e3 * pct(lat_p, 50):.1f} ms p99 {1e3 * pct(lat_p, 99):.1f} ms, "
-        f"max active {st_p['max_active']}")
-    log("[serve] served mixed, saturation (all requests at t=0)")
-    lat_s, e_ss, span_s, st_s = served(reqs, gabi, np.zeros(count), gabi.SOLVE_MIXED_IR, tol,
-                                       budget, max_slots)
-    log(f"[serve]   {count / span_s:.2f} solves/s, max active {st_s['max_active']}")
+    sweep = []
+    for cap in caps:
+        log(f"[serve] served mixed (round cap: {cap_name(cap)}), Poisson arrivals at "
+            f"{rate:.2f}/s")
+        lat_p, e_sv, span_p, st_p = served(reqs, gabi, arrivals, gabi.SOLVE_MIXED_IR, tol,
+                                           budget, max_slots, cap)
+        log(f"[serve]   p50 {1e3 * pct(lat_p, 50):.1f} ms p99 {1e3 * pct(lat_p, 99):.1f} ms, "
+            f"max active {st_p['max_active']}")
+        log("[serve] served mixed, saturation (all requests at t=0)")
+        lat_s, e_ss, span_s, st_s = served(reqs, gabi, np.zeros(count), gabi.SOLVE_MIXED_IR,
+                                           tol, budget, max_slots, cap)
+        log(f"[serve]   {count / span_s:.2f} solves/s, max active {st_s['max_active']}")
+        sweep.append((cap, lat_p, e_sv, span_p, st_p, lat_s, e_ss, span_s, st_s))
+    cap, lat_p, e_sv, span_p, st_p, lat_s, e_ss, span_s, st_s = sweep[0]
 
     def block(service, energies, lat_poisson, lat_sat, capacity, extra=None):
         d = {"solves_per_s": round(capacity, 3),
@@ -213,7 +241,14 @@ def run(count=64, max_slots=32, budget_gib=16.0, tol=TOL, workers=16, problems=N
         "energy_rel_err_vs_fp64_max": float(max(rel(e_sv).max(), rel(e_ss).max())),
         "max_active_poisson": st_p["max_active"], "max_active_saturated": st_s["max_active"],
         "rounds_saturated": st_s["rounds"], "peak_bytes": st_s["peak_bytes"],
-        "poisson_makespan_s": round(span_p, 3)})
+        "poisson_makespan_s": round(span_p, 3), "round_cap": cap_name(cap)})
+    if len(sweep) > 1:
+        out["cap_sweep"] = [
+            {"round_cap": cap_name(c), "solves_per_s": round(count / ss, 3),
+             "p50_ms": round(1e3 * pct(lp, 50), 2), "p90_ms": round(1e3 * pct(lp, 90), 2),
+             "p99_ms": round(1e3 * pct(lp, 99), 2), "max_ms": round(1e3 * float(np.max(lp)), 2),
+             "energy_rel_err_vs_fp64_max": float(max(rel(ep).max(), rel(es).max()))}
+            for c, lp, ep, sp, stp, ls, es, ss, sts in sweep]
     out["speedup_served_over_plain_fp64"] = round(
         out["served_mixed"]["solves_per_s"] / out["plain_fp64"]["solves_per_s"], 3)
     out["p99_ratio_served_over_plain_fp64"] = round(
@@ -229,8 +264,11 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--tol", type=float, default=TOL)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--caps", default="none",
+                    help="round caps of the served runs, comma-separated: 'none' or "
+                         "slack:floor_elements (the first is reported as served_mixed)")
     a = ap.parse_args(argv)
-    res = run(a.requests, a.max_slots, a.budget_gib, a.tol, a.workers)
+    res = run(a.requests, a.max_slots, a.budget_gib, a.tol, a.workers, caps=parse_caps(a.caps))
     print(json.dumps(res), flush=True)
 
 
