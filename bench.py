@@ -485,6 +485,9 @@ def main():
                     help="requests of the serving stream to serve after the single-solve "
                          "timing (0: skip; the stream has 512)")
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-caps", default=None,
+                    help="round caps of the served runs (serve.py --caps; default: "
+                         "slack 0.25 and floor 32768, then none)")
     ap.add_argument("--sequence-steps", type=int, default=8,
                     help="nearby problems solved cold and warm-started after the timing, "
                          "on the secondary workload (0: skip)")
@@ -566,8 +569,9 @@ def main():
         line["treecode"] = tree_crossover(gabi, torch)
     if serve_problems is not None:
         log(f"[bench] serving {args.serve_requests} requests")
-        line["serving"] = serve.run(args.serve_requests, args.serve_slots,
-                                    problems=serve_problems)
+        line["serving"] = serve.run(
+            args.serve_requests, args.serve_slots, problems=serve_problems,
+            caps=serve.parse_caps(args.serve_caps or serve.DEFAULT_CAPS))
         line["serving"]["workload"] = SERVING_WORKLOAD
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (oracle, ~{args.cpu_seconds:.0f} s + a small solve)")
