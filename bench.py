@@ -363,7 +363,7 @@ def warm_sequence(ctx, gabi, p, steps):
 TREE_OPTS = (0.7, 5, 256)   # theta, degree, leaf size of the treecode timing
 
 
-def tree_crossover(gabi, torch, nus=(16, 32, 64, 96, 128), reps=3):
+def tree_crossover(gabi, torch, nus=(16, 32, 40, 48, 56, 64, 96, 128), reps=3):
     """Direct-sum (FP64 and FP32-pair) against treecode (FP64) products on
     geodesic spheres of about 4 elements per square Angstrom: per-product
     device time (HIP events on the context's stream, averaged over `reps`)
@@ -414,12 +414,15 @@ def tree_crossover(gabi, torch, nus=(16, 32, 64, 96, 128), reps=3):
         log(f"[bench] tree N={n}: direct {t64:.3f} ms (fp32-pair {t32:.3f}), tree {t_tree:.3f} "
             f"ms, err {err:.2e}")
     faster = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp64_ms"]]
+    faster32 = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp32_pair_ms"]]
     return {"opts": {"theta": theta, "degree": degree, "leaf_size": leaf},
             "method": "barycentric Lagrange treecode (particle-cluster, target batches), FP64",
             "rows": rows,
             "crossover_N_vs_fp64": faster[0] if faster else None,
+            "crossover_N_vs_fp32_pair": faster32[0] if faster32 else None,
             "crossover_note": "smallest measured N with the treecode product faster than "
-                              "the direct FP64 product (None: not within the sizes measured)"}
+                              "the direct FP64 (FP32-pair) product (None: not within the sizes "
+                              "measured)"}
 
 
 def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves):

@@ -144,27 +144,27 @@ __device__ __forceinline__ void pair_f32(
 // Symmetric evaluation: one unordered pair of elements a (target i) and b
 // (target j) gives both the (target i, source j) and the (target j, source i)
 // terms.  With m = t nu (t = W phi / (4 pi)) and d = x_i - x_j:
-//   d . m_j = t_j (d . nu_j),   nu_i . m_j = t_j n,   n = nu_i . nu_j,
-//   d . m_i = t_i (d . nu_i),   nu_j . m_i = t_i n,
-// so the (j, i) term, which uses the separation -d, the normal of j and the
-// weights of i,
-//   top_j += rinv [ (1-E) s_i - (eps A - 1) t_i u_x rinv^2 ]
-//   bot_j += rinv^3 [ -u_j ((A/eps - 1) s_i + (B-3) t_i u_x rinv^2)
-//                     + (A-1) t_i n ],        u_x = d . nu_i, u_j = d . nu_j,
-// shares with the (i, j) term rho, 1/rho, E, A, B and the three dot products.
-// Both top terms are written with the shared factors P = (1-E) rinv and
-// Q = (eps A - 1) rinv^3:  top_i += P s_j + Q t_j u_j,
-// top_j += P s_i - Q t_i u_x.
-// The (i, j) term accumulates into top/bot, the (j, i) term into ctop/cbot.
+//   d . m_j = t_j u_j,  nu_i . m_j = t_j n,  d . m_i = t_i u_x,
+//   nu_j . m_i = t_i n,  u_x = d . nu_i, u_j = d . nu_j, n = nu_i . nu_j,
+// and the (j, i) term uses the separation -d.  Written with the factors
+//   P = (1-E) rinv,  Q = (eps A - 1) rinv^3,  R = (A/eps - 1) rinv^3,
+//   Y = rinv^3 [(A-1) n - (B-3) rinv^2 u_x u_j],
+// which the two terms share, the four sums are
+//   top_i += P s_j + (Q u_j) t_j,      bot_i += (R u_x) s_j + Y t_j,
+//   top_j += P s_i - (Q u_x) t_i,      bot_j += -(R u_j) s_i + Y t_i,
+// the same quantities as bot = rinv^3 [u_x ((A/eps-1) s - (B-3) w rinv^2)
+// + (A-1) q_n] of the pair form with w = t u_j, q_n = t n.
+// The (i, j) terms accumulate into top/bot, the (j, i) terms into ctop/cbot
+// (sym_f32) or are returned as vt, vb (sym_f64_terms).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SymElem {  // one element as a target and as a source
     T x, y, z, nx, ny, nz, s, t;
 };
 
-__device__ __forceinline__ void sym_f64(const PairConstF64 &c, const SymElem<double> &a,
-                                        const SymElem<double> &b, double &top, double &bot,
-                                        double &ctop, double &cbot) {
+__device__ __forceinline__ void sym_f64_terms(const PairConstF64 &c, const SymElem<double> &a,
+                                              const SymElem<double> &b, double &top,
+                                              double &bot, double &vt, double &vb) {
     const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
     const double rinv = rsqrt_f64(r2);
@@ -174,23 +174,18 @@ __device__ __forceinline__ void sym_f64(const PairConstF64 &c, const SymElem<dou
     const double E = exp_neg_f64(tau);
     const double A = __builtin_fma(E, tau, E);
     const double B3 = __builtin_fma(E, __builtin_fma(tau, tau + 3.0, 3.0), -3.0);
-    const double a1 = __builtin_fma(A, c.inv_eps, -1.0);
-    const double a2 = __builtin_fma(c.eps, A, -1.0);
-    const double B3r2 = B3 * rinv2;
     const double ux = __builtin_fma(dx, a.nx, __builtin_fma(dy, a.ny, dz * a.nz));
     const double uj = __builtin_fma(dx, b.nx, __builtin_fma(dy, b.ny, dz * b.nz));
     const double nn = __builtin_fma(a.nx, b.nx, __builtin_fma(a.ny, b.ny, a.nz * b.nz));
-    const double P = __builtin_fma(-E, rinv, rinv), Q = a2 * rinv3;
-    // target i, source j
-    const double w = b.t * uj, qn = b.t * nn;
-    top = __builtin_fma(P, b.s, __builtin_fma(Q, w, top));
-    const double k3 = __builtin_fma(a1, b.s, -B3r2 * w);
-    bot = __builtin_fma(__builtin_fma(ux, k3, __builtin_fma(A, qn, -qn)), rinv3, bot);
-    // target j, source i
-    const double wm = a.t * ux, qj = a.t * nn;
-    ctop = __builtin_fma(P, a.s, __builtin_fma(-Q, wm, ctop));
-    const double k3j = __builtin_fma(a1, a.s, B3r2 * wm);
-    cbot = __builtin_fma(__builtin_fma(-uj, k3j, __builtin_fma(A, qj, -qj)), rinv3, cbot);
+    const double P = __builtin_fma(-E, rinv, rinv);
+    const double Q = __builtin_fma(c.eps, A, -1.0) * rinv3;
+    const double R = __builtin_fma(A, c.inv_eps, -1.0) * rinv3;
+    const double Bu = (B3 * rinv2) * ux;
+    const double Y = __builtin_fma(-Bu, uj, __builtin_fma(A, nn, -nn)) * rinv3;
+    top = __builtin_fma(P, b.s, __builtin_fma(Q * uj, b.t, top));
+    bot = __builtin_fma(R * ux, b.s, __builtin_fma(Y, b.t, bot));
+    vt = __builtin_fma(P, a.s, -(Q * ux) * a.t);
+    vb = __builtin_fma(-(R * uj), a.s, Y * a.t);
 }
 
 __device__ __forceinline__ void sym_f32(const PairConstF32 &c, const SymElem<float> &a,
@@ -206,21 +201,18 @@ __device__ __forceinline__ void sym_f32(const PairConstF32 &c, const SymElem<flo
     const float E = __builtin_amdgcn_exp2f(rho * c.neg_kappa_log2e);
     const float A = __builtin_fmaf(E, tau, E);
     const float B3 = __builtin_fmaf(E, __builtin_fmaf(tau, tau + 3.0f, 3.0f), -3.0f);
-    const float a1 = __builtin_fmaf(A, c.inv_eps, -1.0f);
-    const float a2 = __builtin_fmaf(c.eps, A, -1.0f);
-    const float B3r2 = B3 * rinv2;
     const float ux = __builtin_fmaf(dx, a.nx, __builtin_fmaf(dy, a.ny, dz * a.nz));
     const float uj = __builtin_fmaf(dx, b.nx, __builtin_fmaf(dy, b.ny, dz * b.nz));
     const float nn = __builtin_fmaf(a.nx, b.nx, __builtin_fmaf(a.ny, b.ny, a.nz * b.nz));
-    const float P = __builtin_fmaf(-E, rinv, rinv), Q = a2 * rinv3;
-    const float w = b.t * uj, qn = b.t * nn;
-    top = __builtin_fmaf(P, b.s, __builtin_fmaf(Q, w, top));
-    const float k3 = __builtin_fmaf(a1, b.s, -B3r2 * w);
-    bot = __builtin_fmaf(__builtin_fmaf(ux, k3, __builtin_fmaf(A, qn, -qn)), rinv3, bot);
-    const float wm = a.t * ux, qj = a.t * nn;
-    ctop = __builtin_fmaf(P, a.s, __builtin_fmaf(-Q, wm, ctop));
-    const float k3j = __builtin_fmaf(a1, a.s, B3r2 * wm);
-    cbot = __builtin_fmaf(__builtin_fmaf(-uj, k3j, __builtin_fmaf(A, qj, -qj)), rinv3, cbot);
+    const float P = __builtin_fmaf(-E, rinv, rinv);
+    const float Q = __builtin_fmaf(c.eps, A, -1.0f) * rinv3;
+    const float R = __builtin_fmaf(A, c.inv_eps, -1.0f) * rinv3;
+    const float Bu = (B3 * rinv2) * ux;
+    const float Y = __builtin_fmaf(-Bu, uj, __builtin_fmaf(A, nn, -nn)) * rinv3;
+    top = __builtin_fmaf(P, b.s, __builtin_fmaf(Q * uj, b.t, top));
+    bot = __builtin_fmaf(R * ux, b.s, __builtin_fmaf(Y, b.t, bot));
+    ctop = __builtin_fmaf(P, a.s, __builtin_fmaf(-(Q * ux), a.t, ctop));
+    cbot = __builtin_fmaf(-(R * uj), a.s, __builtin_fmaf(Y, a.t, cbot));
 }
 
 }  // namespace gabi
