@@ -273,6 +273,18 @@ __device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
     }
 }
 
+// In a launch that may be skipped (a later step of a GMRES cycle that can
+// have ended), a workgroup returns at once when every molecule's cycle has
+// ended: handing out the tiles one by one only to skip each would cost the
+// queue's atomics and barriers for every tile (about 0.7 ms per launch at
+// N = 81,920).  The flags are set by earlier launches and do not change
+// during this one, so every workgroup takes the same decision.
+__device__ __forceinline__ bool all_done(const Mol *__restrict__ mols, int nmol) {
+    for (int m = 0; m < nmol; ++m)
+        if (!load_done(mols[m].st)) return false;
+    return true;
+}
+
 // One workgroup per tile (flat) or a fixed grid draining the tile queue
 // (persistent).  The loop exits for every workgroup once the counter passes
 // the end of the list.  The FP32-pair variant is held to 7 waves per SIMD
@@ -280,12 +292,13 @@ __device__ __forceinline__ void pair_tile(const Mol &M, int rb, int sp,
 // needs its registers and runs at 4.
 template <bool MIXED, int R>
 __global__ __launch_bounds__(kBlock, MIXED ? 7 : 1) void pair_kernel(
-    const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
+    const Mol *__restrict__ mols, int nmol, const int4 *__restrict__ tiles, int ntiles,
     int *__restrict__ counter, int persistent, int skip) {
     using T4 = typename PairView<MIXED>::T4;
     __shared__ T4 s_pos[kTile];
     __shared__ T4 s_w[kTile];
     __shared__ int s_next;
+    if (skip && all_done(mols, nmol)) return;
     for (int t = (int)blockIdx.x; t < ntiles;
          t = next_tile(persistent, t, ntiles, counter, &s_next)) {
         const int4 tile = tiles[t];
@@ -498,7 +511,7 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int slot,
 // The FP32-pair variant is held to 8 waves per SIMD (at most 64 VGPRs).
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
-    const Mol *__restrict__ mols, const int4 *__restrict__ tiles, int ntiles,
+    const Mol *__restrict__ mols, int nmol, const int4 *__restrict__ tiles, int ntiles,
     const int *__restrict__ xoff, int *__restrict__ xcnt, int persistent, int skip) {
     using T4 = typename PairView<MIXED>::T4;
     // two 4-vectors per element of block J, each chunk stored twice; the
@@ -517,6 +530,7 @@ __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
         if (!(skip && load_done(M.st)))
             sym_tile<MIXED>(M, tile.y, tile.z, tile.w & 0xffff, s_stage, s_cacc);
     };
+    if (skip && all_done(mols, nmol)) return;
     if (!persistent) {
         if ((int)blockIdx.x < ntiles) run((int)blockIdx.x);
         return;
@@ -743,12 +757,13 @@ static void pair_group(Batch &b, hipStream_t s, const int4 *tiles, int ntiles, i
     // the counters are zero: set by the batch upload, rearmed by every finish
     // (and, for the symmetric queues, by the fold between passes)
     const int grid = b.persistent ? std::min(ntiles, grid_cap) : ntiles;
+    const int nmol = (int)b.slots.size();
     if constexpr (R == 0)
         hipLaunchKernelGGL((sym_pair_kernel<MIXED>), dim3(grid), dim3(kBlock), 0, s, b.d_mols,
-                           tiles, ntiles, xoff, counter, (int)b.persistent, (int)skip);
+                           nmol, tiles, ntiles, xoff, counter, (int)b.persistent, (int)skip);
     else
         hipLaunchKernelGGL((pair_kernel<MIXED, R>), dim3(grid), dim3(kBlock), 0, s, b.d_mols,
-                           tiles, ntiles, counter, (int)b.persistent, (int)skip);
+                           nmol, tiles, ntiles, counter, (int)b.persistent, (int)skip);
 }
 
 // Records e on s; on a stream under capture the record becomes an
