@@ -352,8 +352,7 @@ __device__ __forceinline__ SymElem<typename PairView<MIXED>::T> sym_load(const M
 
 template <bool MIXED>
 __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int slot,
-                                         typename PairView<MIXED>::T4 *s_stage,
-                                         double *s_cacc) {
+                                         typename PairView<MIXED>::T4 *s_stage) {
     using T = typename PairView<MIXED>::T;
     using T4 = typename PairView<MIXED>::T4;
     const int n = M.n;
@@ -394,7 +393,7 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int slot,
                              q.w * q.y, q.w * q.z, top, bot);
                 }
             }
-        } else if constexpr (MIXED) {
+        } else {
             T ctop = T(0), cbot = T(0);
             const int from = rotate_from();
             // the next element is read one step ahead: step s reads element
@@ -412,63 +411,25 @@ __device__ __forceinline__ void sym_tile(const Mol &M, int I, int J, int slot,
                     const T4 pn = pa[7 - u], qn = pb[7 - u];
                     __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the step
                     const SymElem<T> b{p.x, p.y, p.z, q.x, q.y, q.z, p.w, q.w};
-                    const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
-                    sym_f32(kc, a, b, top, bot, ctop, cbot);
+                    if constexpr (MIXED) {
+                        const PairConstF32 kc{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
+                        sym_f32(kc, a, b, top, bot, ctop, cbot);
+                    } else {
+                        const PairConstF64 kc{M.kappa, M.eps, M.inv_eps};
+                        sym_f64(kc, a, b, top, bot, ctop, cbot);
+                    }
                     ctop = wave_rotate(ctop, from);
                     cbot = wave_rotate(cbot, from);
                     p = pn;
                     q = qn;
                 }
             }
+            // once every wave is past chunk c, its (x, y, z, s) entries (both
+            // copies, 128 4-vectors) are free: they take each wave's 64 column
+            // sums of top and bot, so no registers carry them across chunks
             static_assert(2 * kBlock <= 4 * 128, "column sums exceed a chunk's entries");
             __syncthreads();
             T *cs = reinterpret_cast<T *>(sa + c * 128);
-            cs[wave * 64 + lane] = ctop;
-            cs[kBlock + wave * 64 + lane] = cbot;
-        } else {
-            // FP64: the (j, i) terms are added in LDS rather than carried in
-            // rotating registers (a DPP rotation of a double costs two VALU
-            // moves per sum and step).  Each wave owns two arrays of 128
-            // doubles (top, bot); at step s lane l adds its term for element
-            // (l - s) mod 64 to entry l + 64 - s, the index it reads the
-            // element's data from, so the 64 lanes touch 64 distinct entries
-            // and element e's terms land in entries e + 64 (steps s <= l) and
-            // e (steps s > l), each in step order.  The column sum is
-            // (entry e + 64) + (entry e): a fixed order.
-            double *ct = s_cacc + wave * 256, *cbt = ct + 128;
-            ct[lane] = 0.0;
-            ct[lane + 64] = 0.0;
-            cbt[lane] = 0.0;
-            cbt[lane + 64] = 0.0;
-            T4 p = ca[0], q = cb[0];
-            const T4 *pa = ca, *pb = cb;
-            // entry lane + 64 - s of step s = 8 g + u is ta[7 - u] in group g
-            double *ta = ct + lane + 65, *tb = cbt + lane + 65;
-#pragma unroll 1
-            for (int g = 0; g < 8; ++g) {
-                pa -= 8;
-                pb -= 8;
-                ta -= 8;
-                tb -= 8;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const T4 pn = pa[7 - u], qn = pb[7 - u];
-                    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the step
-                    const SymElem<T> b{p.x, p.y, p.z, q.x, q.y, q.z, p.w, q.w};
-                    const PairConstF64 kc{M.kappa, M.eps, M.inv_eps};
-                    double vt, vb;
-                    sym_f64_terms(kc, a, b, top, bot, vt, vb);
-                    __hip_atomic_fetch_add(ta + 7 - u, vt, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __hip_atomic_fetch_add(tb + 7 - u, vb, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                    p = pn;
-                    q = qn;
-                }
-            }
-            __syncthreads();
-            const double ctop = ct[lane + 64] + ct[lane], cbot = cbt[lane + 64] + cbt[lane];
-            double *cs = reinterpret_cast<double *>(sa + c * 128);
             cs[wave * 64 + lane] = ctop;
             cs[kBlock + wave * 64 + lane] = cbot;
         }
@@ -517,18 +478,11 @@ __global__ __launch_bounds__(kBlock, MIXED ? 8 : 1) void sym_pair_kernel(
     // two 4-vectors per element of block J, each chunk stored twice; the
     // first copies also take the column sums (2 x 4 waves x 64 per chunk)
     __shared__ T4 s_stage[4 * kTile];
-    // FP64: the column-sum arrays of the four waves (2 x 128 doubles each);
-    // the tile index handed out between tiles shares their last entry
-    // (written and read only between tiles, before the next tile's staging
-    // barrier), which keeps the kernel's LDS at 40 KiB, four workgroups per CU
-    constexpr int kCacc = MIXED ? 2 : kBlock / 64 * 256;
-    __shared__ double s_cacc[kCacc];
-    int &s_next = *reinterpret_cast<int *>(&s_cacc[kCacc - 1]);
+    __shared__ int s_next;
     auto run = [&](int t) {
         const int4 tile = tiles[t];
         const Mol &M = mols[tile.x];
-        if (!(skip && load_done(M.st)))
-            sym_tile<MIXED>(M, tile.y, tile.z, tile.w & 0xffff, s_stage, s_cacc);
+        if (!(skip && load_done(M.st))) sym_tile<MIXED>(M, tile.y, tile.z, tile.w & 0xffff, s_stage);
     };
     if (skip && all_done(mols, nmol)) return;
     if (!persistent) {

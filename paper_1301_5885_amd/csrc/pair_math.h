@@ -154,17 +154,16 @@ __device__ __forceinline__ void pair_f32(
 //   top_j += P s_i - (Q u_x) t_i,      bot_j += -(R u_j) s_i + Y t_i,
 // the same quantities as bot = rinv^3 [u_x ((A/eps-1) s - (B-3) w rinv^2)
 // + (A-1) q_n] of the pair form with w = t u_j, q_n = t n.
-// The (i, j) terms accumulate into top/bot, the (j, i) terms into ctop/cbot
-// (sym_f32) or are returned as vt, vb (sym_f64_terms).
+// The (i, j) terms accumulate into top/bot, the (j, i) terms into ctop/cbot.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SymElem {  // one element as a target and as a source
     T x, y, z, nx, ny, nz, s, t;
 };
 
-__device__ __forceinline__ void sym_f64_terms(const PairConstF64 &c, const SymElem<double> &a,
-                                              const SymElem<double> &b, double &top,
-                                              double &bot, double &vt, double &vb) {
+__device__ __forceinline__ void sym_f64(const PairConstF64 &c, const SymElem<double> &a,
+                                        const SymElem<double> &b, double &top, double &bot,
+                                        double &ctop, double &cbot) {
     const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
     const double rinv = rsqrt_f64(r2);
@@ -184,8 +183,8 @@ __device__ __forceinline__ void sym_f64_terms(const PairConstF64 &c, const SymEl
     const double Y = __builtin_fma(-Bu, uj, __builtin_fma(A, nn, -nn)) * rinv3;
     top = __builtin_fma(P, b.s, __builtin_fma(Q * uj, b.t, top));
     bot = __builtin_fma(R * ux, b.s, __builtin_fma(Y, b.t, bot));
-    vt = __builtin_fma(P, a.s, -(Q * ux) * a.t);
-    vb = __builtin_fma(-(R * uj), a.s, Y * a.t);
+    ctop = __builtin_fma(P, a.s, __builtin_fma(-(Q * ux), a.t, ctop));
+    cbot = __builtin_fma(-(R * uj), a.s, __builtin_fma(Y, a.t, cbot));
 }
 
 __device__ __forceinline__ void sym_f32(const PairConstF32 &c, const SymElem<float> &a,

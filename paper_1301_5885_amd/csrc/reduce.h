@@ -55,15 +55,25 @@ namespace gabi {
 // receives lane (l - 1) mod 64's value, so after 64 rotations every value is
 // back in its lane.  All 64 lanes must be active.
 //
-// The rotation goes through the LDS crossbar (ds_bpermute; `from` is the
-// byte address of the source lane, rotate_from()), which leaves the VALU to
-// the pair arithmetic: measured 2-4% faster for the FP32 symmetric kernel at
-// N >= 46,080.  (The FP64 kernel adds its column sums in LDS instead.)
+// The float rotation goes through the LDS crossbar (ds_bpermute; `from` is
+// the byte address of the source lane, rotate_from()), which leaves the VALU
+// to the pair arithmetic: measured 2-4% faster for the FP32 symmetric kernel
+// at N >= 46,080.  The double rotation uses DPP wave_ror:1 on each half: two
+// crossbar moves per double cost the FP64 kernel (four waves per SIMD) 3%,
+// and adding the FP64 column sums in per-wave LDS arrays (ds_add_f64) instead
+// of rotating them was 2% slower at N = 327,680 (measured on one box).
 __device__ __forceinline__ int rotate_from() {
     return (int)(((threadIdx.x & 63u) + 63u) & 63u) << 2;
 }
 __device__ __forceinline__ float wave_rotate(float v, int from) {
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(from, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double wave_rotate(double v, int) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, 0x13C, 0xf, 0xf, true);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0x13C, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
 }
 
 }  // namespace gabi
