@@ -69,8 +69,16 @@ typedef enum {
 /* Solver modes.                                                           */
 typedef enum {
     GABI_SOLVE_FP64 = 0,     /* restarted GMRES(m) on the FP64 product       */
-    GABI_SOLVE_MIXED_IR = 1  /* FP64 iterative refinement around GMRES(m) on
+    GABI_SOLVE_MIXED_IR = 1, /* FP64 iterative refinement around GMRES(m) on
                                 the FP32-pair product                        */
+    GABI_SOLVE_TREE_IR = 2   /* FP64 iterative refinement around GMRES(m) on
+                                the treecode product (gabi_tree_matvec), for
+                                large surfaces (Section 1 and Section 4 name
+                                tree codes as the route past the direct
+                                sum): the residuals are the FP64 direct
+                                product's, so the solve meets the same
+                                stopping rule.  Single contexts only
+                                (gabi_batch_solve and servers: GABI_EINVAL)  */
 } gabi_solve_mode;
 
 typedef struct {
@@ -95,6 +103,9 @@ typedef struct {
                           the warm start of a sequence of nearby problems,
                           Section 4); 0, or no such solution, starts from
                           zero.  Batch and server calls ignore it (0)         */
+    double tree_theta;   /* TREE_IR: treecode options of the inner products  */
+    int32_t tree_degree; /* (gabi_tree_opts; defaults 0.7, 5, 256)            */
+    int32_t tree_leaf;
 } gabi_solve_opts;
 
 typedef struct {
@@ -108,6 +119,7 @@ typedef struct {
     double seconds;       /* wall time of the call                            */
     int32_t warm_start;   /* 1 if the initial guess was not zero (x0 given or
                              the previous solution, see x0_previous)          */
+    int64_t matvecs_tree; /* treecode products (TREE_IR)                      */
 } gabi_solve_info;
 
 /* Fill opts with the defaults listed above.                                */

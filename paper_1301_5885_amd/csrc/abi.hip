@@ -175,13 +175,20 @@ int opts_check(const gabi_solve_opts *in, gabi_solve_opts *o, std::string &msg) 
         msg = "tol must be > 0";
         return GABI_EINVAL;
     }
-    if (o->mode != GABI_SOLVE_FP64 && o->mode != GABI_SOLVE_MIXED_IR) {
+    if (o->mode != GABI_SOLVE_FP64 && o->mode != GABI_SOLVE_MIXED_IR &&
+        o->mode != GABI_SOLVE_TREE_IR) {
         msg = "unknown solve mode";
         return GABI_EINVAL;
     }
-    if (o->mode == GABI_SOLVE_MIXED_IR &&
+    if (o->mode != GABI_SOLVE_FP64 &&
         (!(o->inner_tol > 0.0) || !(o->inner_tol < 1.0) || o->max_outer < 1)) {
         msg = "need 0 < inner_tol < 1 and max_outer >= 1";
+        return GABI_EINVAL;
+    }
+    if (o->mode == GABI_SOLVE_TREE_IR &&
+        (!(o->tree_theta >= 0.0 && o->tree_theta < 1.0) || o->tree_degree < 1 ||
+         o->tree_degree > 8 || o->tree_leaf < 1 || o->tree_leaf > kBlock)) {
+        msg = "treecode options: theta in [0, 1), degree in [1, 8], leaf in [1, 256]";
         return GABI_EINVAL;
     }
     if (o->x0_previous != 0 && o->x0_previous != 1) {
@@ -360,6 +367,9 @@ void gabi_default_opts(gabi_solve_opts *o) {
     o->max_outer = 20;
     o->use_graph = 1;
     o->x0_previous = 0;
+    o->tree_theta = 0.7;
+    o->tree_degree = 5;
+    o->tree_leaf = 256;
 }
 
 int gabi_create(gabi_ctx **out, int device) {
@@ -588,12 +598,30 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
     if ((rc = opts_check(opts, &o, msg))) return fail(ctx, rc, msg);
     if ((rc = ensure_slot(ctx, o.restart))) return rc;
     Slot &sl = ctx->slot;
-    const int mode = o.mode == GABI_SOLVE_MIXED_IR ? kModeMixed : kModeFP64;
+    const bool tree = o.mode == GABI_SOLVE_TREE_IR;
+    // the treecode refinement runs the mixed solver's rounds with treecode
+    // cycle products
+    const int mode = o.mode == GABI_SOLVE_FP64 ? kModeFP64 : kModeMixed;
     slot_set_mode(sl, mode);
     set_solve_targets(sl, o.tol, o.inner_tol, o.maxit);
     sl.mol.m = o.restart;
+    if (tree) {
+        const gabi_tree_opts to{o.tree_theta, o.tree_degree, o.tree_leaf};
+        if ((rc = tree_for_solve(ctx, &to))) return rc;
+    }
     if ((rc = sync_batch(ctx))) return rc;
     Batch &b = ctx->batch;
+    {
+        // a round captured with other cycle products (or another tree) is
+        // recorded again
+        const TreeState *tr = tree ? ctx->tree : nullptr;
+        const int64_t gen = tr ? tree_generation(*tr) : -1;
+        if (b.tree != tr || b.tree_gen != gen) {
+            release_graph(b);
+            b.tree = tr;
+            b.tree_gen = gen;
+        }
+    }
     Timer t = make_timer(ctx);
     const bool graph = o.use_graph != 0;
     const size_t bytes = sizeof(double) * 2 * ctx->n;
@@ -628,7 +656,7 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
     out.restarts = rounds;
     const int64_t extra = warm ? 1 : 0;
     if (mode == kModeMixed) {
-        out.matvecs_fp32 = st.iters;
+        (tree ? out.matvecs_tree : out.matvecs_fp32) = st.iters;
         out.matvecs_fp64 = rounds + extra;
         out.outer = rounds;
     } else {

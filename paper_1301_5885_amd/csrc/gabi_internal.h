@@ -218,6 +218,11 @@ struct Batch {
     // overwrites
     std::vector<std::pair<hipEvent_t, hipEvent_t>> graph_events[2];
     bool graph_timed = false;
+    // treecode refinement (a single context's batch): the inner products of
+    // a cycle are the context's treecode products; tree_gen identifies the
+    // tree the captured round was recorded with
+    const struct TreeState *tree = nullptr;
+    int64_t tree_gen = -1;
 };
 
 int batch_build(Batch &b, hipStream_t stream, std::string &err);
@@ -227,6 +232,16 @@ void release_graph(Batch &b);  // the captured round and its events
 
 struct TreeState;                // treecode product (tree.hip)
 void tree_free(TreeState *t);
+// the context's tree for these options, built or rebuilt as needed
+int tree_for_solve(gabi_ctx *ctx, const gabi_tree_opts *o);
+// treecode sums of u (2n, element order) into slot (top at [j], bot at
+// [n + j]); with skip, nothing once M's cycle has ended
+void launch_tree_sums(const TreeState &T, hipStream_t s, const Mol &M, const double *u,
+                      double *slot, bool skip);
+int64_t tree_generation(const TreeState &T);  // changes with every rebuild
+// pseudo-precision of the Arnoldi finish for a product held as one FP64
+// partial-sum slot (the treecode refinement's inner products)
+constexpr int kPrecTree = 2;
 
 }  // namespace gabi
 

@@ -16,8 +16,10 @@
 // residual, and the start of the next cycle.  For the FP64 solver the cycle
 // products are FP64 (restarted GMRES exactly as the paper runs it); for the
 // mixed solver they are FP32-pair products while the residual that starts
-// every cycle is FP64 (iterative refinement whose inner solve is one cycle).
-// The host reads one status record per molecule per round.
+// every cycle is FP64 (iterative refinement whose inner solve is one cycle);
+// the treecode refinement of a single context takes the cycle products from
+// the treecode instead.  The host reads one status record per molecule per
+// round.
 //
 // All Krylov vectors, H, the rotations and every reduction are FP64.
 #include <algorithm>
@@ -283,9 +285,18 @@ void enqueue_round(Batch &b, hipStream_t s, const Timer *t) {
     const int m = b.slots.empty() ? 0 : b.slots[0]->mol.m;
     for (int j = 0; j < m; ++j) {
         // the prep of step j > 0 also runs the Givens step that closes j - 1
-        launch_prep(b, s, prec, j == 0 ? kPrepCycle0 : kPrepCycleJ, j, true);
-        launch_pair(b, s, prec, true, t);
-        launch_finish(b, s, prec, kFinishDot, j, true);
+        if (b.tree) {
+            // treecode refinement: V_j from the FP64 prep, its treecode sums
+            // as the single partial slot of the Arnoldi finish
+            const Mol &M = b.slots[0]->mol;
+            launch_prep(b, s, GABI_FP64, j == 0 ? kPrepCycle0 : kPrepCycleJ, j, true);
+            launch_tree_sums(*b.tree, s, M, M.V + (size_t)j * 2 * M.n, M.part, true);
+            launch_finish(b, s, kPrecTree, kFinishDot, j, true);
+        } else {
+            launch_prep(b, s, prec, j == 0 ? kPrepCycle0 : kPrepCycleJ, j, true);
+            launch_pair(b, s, prec, true, t);
+            launch_finish(b, s, prec, kFinishDot, j, true);
+        }
         if (j > 0)
             hipLaunchKernelGGL(gram_kernel, dim3(b.n_blas, 2 * j), dim3(kBlock), 0, s,
                                b.d_mols, b.d_blas, j);

@@ -572,15 +572,16 @@ __global__ __launch_bounds__(kBlock * kFinishQ) void finish_kernel(
     if (skip && load_done(M.st)) return;
     const int n = M.n, nb = M.nb;
     const int q = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
-    const int splits = precision == GABI_FP64 ? M.last64 : M.last32;
-    const bool multi = (precision == GABI_FP64 ? M.np64 : M.np32) > 1;
+    // kPrecTree: the treecode sums, one FP64 slot
+    const int splits = precision == kPrecTree ? 1 : precision == GABI_FP64 ? M.last64 : M.last32;
+    const bool multi = precision != kPrecTree && (precision == GABI_FP64 ? M.np64 : M.np32) > 1;
     const int p0 = q * splits / kFinishQ, p1 = (q + 1) * splits / kFinishQ;
     const double *v = MODE == kFinishDot ? M.V + (size_t)j * 2 * n
                     : MODE == kFinishRes ? M.res_x
                                          : M.u;
     double *out = MODE == kFinishDot ? M.w : MODE == kFinishRes ? M.res_out : M.y;
     const double dt = M.d_top, db = M.d_bot;
-    const bool f32 = precision != GABI_FP64 && M.sym32;  // float partial sums
+    const bool f32 = precision == GABI_FP32_PAIR && M.sym32;  // float partial sums
     const float *pf = reinterpret_cast<const float *>(M.part);
     double s = 0.0;
     for (int base = e.y * kBlock; base < n; base += nb * kBlock) {
@@ -787,7 +788,7 @@ void launch_pair(Batch &b, hipStream_t s, int precision, bool skip, const Timer 
 
 void launch_finish(const Batch &b, hipStream_t s, int precision, int mode, int j, bool skip) {
     const dim3 g(b.n_blas), blk(kBlock * kFinishQ);
-    int *c = b.d_counter + (precision == GABI_FP64 ? 0 : kCountersPerPrecision);
+    int *c = b.d_counter + (precision == GABI_FP32_PAIR ? kCountersPerPrecision : 0);
     if (mode == kFinishDot)
         hipLaunchKernelGGL(finish_kernel<kFinishDot>, g, blk, 0, s, b.d_mols, b.d_blas,
                            precision, j, (int)skip, c);

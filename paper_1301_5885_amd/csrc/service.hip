@@ -534,6 +534,7 @@ int gabi_batch_solve(int device, int64_t nprob, const gabi_problem *probs,
     gabi_solve_opts o;
     std::string err;
     if (opts_check(opts, &o, err)) return GABI_EINVAL;
+    if (o.mode == GABI_SOLVE_TREE_IR) return GABI_EINVAL;  // single contexts only
     std::vector<Staged> staged((size_t)nprob);
     int64_t total = 0;
     std::vector<int64_t> offs((size_t)nprob);
@@ -604,7 +605,8 @@ int gabi_server_create(gabi_server **out, int device, int64_t budget_bytes,
     *out = nullptr;
     auto srv = std::make_unique<gabi_server>();
     std::string err;
-    if (opts_check(opts, &srv->opts, err)) return GABI_EINVAL;
+    if (opts_check(opts, &srv->opts, err) || srv->opts.mode == GABI_SOLVE_TREE_IR)
+        return GABI_EINVAL;  // the treecode refinement is for single contexts
     srv->max_slots = max_slots;
     srv->arena = std::make_unique<Arena>(budget_bytes);
     srv->stats.budget_bytes = budget_bytes;

@@ -30,7 +30,12 @@
 // every target of the batch is served by 256/P threads (P the batch size
 // rounded up to a power of two) that take interleaved sources, their sums
 // added in thread order; the item writes one partial per target, and
-// tree_finish adds a batch's items in list order.  The pair arithmetic is
+// tree_finish adds a batch's items in list order.  In the treecode
+// refinement (GABI_SOLVE_TREE_IR) the same kernels form the inner products of
+// a GMRES cycle: the finish then stores the sums in element order as the
+// molecule's single partial-sum slot, the Arnoldi finish applies the diagonal
+// and the dot products, and every kernel returns at once once the cycle has
+// ended (the round's later steps).  The pair arithmetic is
 // the direct product's, FP64.  Every sum is taken in a fixed order, so
 // results are reproducible bit for bit.
 #include <algorithm>
@@ -39,6 +44,7 @@
 #include <functional>
 #include <vector>
 
+#include "arnoldi.h"
 #include "gabi_internal.h"
 #include "pair_math.h"
 
@@ -77,6 +83,7 @@ struct TreeState {
     int4 *items = nullptr;     // (batch, list begin, list end, 0)
     double2 *ipart = nullptr;  // [item][kBlock] partial (top, bot) per target
     int n_items = 0;
+    int64_t generation = 0;  // counts rebuilds (captured rounds compare it)
 };
 
 namespace {
@@ -256,7 +263,9 @@ struct TreeDev {
 };
 
 // Weights of the product in tree order: s = W psi/(4 pi), m = W phi nu/(4 pi).
-__global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const double *__restrict__ u) {
+__global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const double *__restrict__ u,
+                                                          const KrylovStatus *st, int skip) {
+    if (skip && load_done(st)) return;
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= T.n) return;
     const int j = T.perm[p];
@@ -273,9 +282,11 @@ __global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const doub
 constexpr int kTreeChunk = 64;
 constexpr int kTreeProxPerThread = (729 + kBlock - 1) / kBlock;
 
-__global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T) {
+__global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T, const KrylovStatus *st,
+                                                             int skip) {
     __shared__ double s_l[3][kTreeChunk][kTreeMaxDeg + 1];
     __shared__ double4 s_w[kTreeChunk];
+    if (skip && load_done(st)) return;
     const int4 cl = T.clusters[blockIdx.x];
     const int deg = T.degree, np1 = deg + 1;
     const double *nodes = T.cheb + (size_t)blockIdx.x * 3 * np1;
@@ -338,10 +349,12 @@ __global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T) {
 // j = t / P (mod G) of every staged chunk, G = 256 / P; the G sums of a
 // target are added in thread order through LDS and stored as the item's
 // partial.
-__global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF64 pc) {
+__global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF64 pc,
+                                                          const KrylovStatus *st, int skip) {
     __shared__ double4 s_pos[kBlock];
     __shared__ double4 s_w[kBlock];
     __shared__ double2 s_sum[kBlock];
+    if (skip && load_done(st)) return;
     const int4 item = T.items[blockIdx.x];
     const int4 bt = T.batches[item.x];
     const int bsz = bt.y - bt.x;
@@ -390,12 +403,19 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
     }
 }
 
-// y = D u - sums at the elements' own indices, a batch's item partials
-// added in list order.
+// MODE kTreeY:    y = D u - sums at the elements' own indices;
+//      kTreeSlot: the sums themselves, top at out[j], bot at out[n + j] (a
+//                 partial-sum slot of the Arnoldi finish).
+// A batch's item partials are added in list order.
+enum TreeFinish { kTreeY = 0, kTreeSlot = 1 };
+
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void tree_finish_kernel(TreeDev T, double d_top,
                                                             double d_bot,
                                                             const double *__restrict__ u,
-                                                            double *__restrict__ y) {
+                                                            double *__restrict__ y,
+                                                            const KrylovStatus *st, int skip) {
+    if (skip && load_done(st)) return;
     const int4 bt = T.batches[blockIdx.x];
     const int tg = (int)threadIdx.x;
     if (tg >= bt.y - bt.x) return;
@@ -406,8 +426,13 @@ __global__ __launch_bounds__(kBlock) void tree_finish_kernel(TreeDev T, double d
         bot += v.y;
     }
     const int j = T.perm[bt.x + tg];
-    y[j] = d_top * u[j] - top;
-    y[T.n + j] = d_bot * u[T.n + j] - bot;
+    if constexpr (MODE == kTreeY) {
+        y[j] = d_top * u[j] - top;
+        y[T.n + j] = d_bot * u[T.n + j] - bot;
+    } else {
+        y[j] = top;
+        y[T.n + j] = bot;
+    }
 }
 
 // ------------------------------------------------------------------ host
@@ -567,6 +592,7 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     GABI_HIP(ctx, up(T.items, items.data(), 16 * items.size()));
     GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
     T.version = ctx->geom_version;
+    ++T.generation;
     T.theta = o->theta;
     T.degree = o->degree;
     T.leaf = o->leaf_size;
@@ -611,13 +637,15 @@ int tree_product(gabi_ctx *ctx, const gabi_tree_opts *o, const double *u_dev, do
         if (e0) (void)hipEventRecord(e0, ctx->stream);
     }
     hipLaunchKernelGGL(tree_prep_kernel, dim3((T.n + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       ctx->stream, d, u_dev);
+                       ctx->stream, d, u_dev, nullptr, 0);
     if (T.n_clusters > 0)
         hipLaunchKernelGGL(tree_weights_kernel, dim3(T.n_clusters), dim3(kBlock), 0, ctx->stream,
-                           d);
-    hipLaunchKernelGGL(tree_eval_kernel, dim3(T.n_items), dim3(kBlock), 0, ctx->stream, d, pc);
-    hipLaunchKernelGGL(tree_finish_kernel, dim3(T.n_batches), dim3(kBlock), 0, ctx->stream, d,
-                       0.5 * (1.0 + eps), 0.5 * (1.0 + 1.0 / eps), u_dev, y_dev);
+                           d, nullptr, 0);
+    hipLaunchKernelGGL(tree_eval_kernel, dim3(T.n_items), dim3(kBlock), 0, ctx->stream, d, pc,
+                       nullptr, 0);
+    hipLaunchKernelGGL(tree_finish_kernel<kTreeY>, dim3(T.n_batches), dim3(kBlock), 0,
+                       ctx->stream, d, 0.5 * (1.0 + eps), 0.5 * (1.0 + 1.0 / eps), u_dev, y_dev,
+                       nullptr, 0);
     if (e0 && e1) {
         (void)hipEventRecord(e1, ctx->stream);
         ctx->pending[2].push_back({e0, e1});
@@ -627,6 +655,26 @@ int tree_product(gabi_ctx *ctx, const gabi_tree_opts *o, const double *u_dev, do
 }
 
 }  // namespace
+
+int tree_for_solve(gabi_ctx *ctx, const gabi_tree_opts *o) { return tree_ensure(ctx, o); }
+
+void launch_tree_sums(const TreeState &T, hipStream_t s, const Mol &M, const double *u,
+                      double *slot, bool skip) {
+    const TreeDev d = tree_dev(T);
+    const PairConstF64 pc{M.kappa, M.eps, M.inv_eps};
+    const int sk = skip ? 1 : 0;
+    hipLaunchKernelGGL(tree_prep_kernel, dim3((T.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       d, u, M.st, sk);
+    if (T.n_clusters > 0)
+        hipLaunchKernelGGL(tree_weights_kernel, dim3(T.n_clusters), dim3(kBlock), 0, s, d, M.st,
+                           sk);
+    hipLaunchKernelGGL(tree_eval_kernel, dim3(T.n_items), dim3(kBlock), 0, s, d, pc, M.st, sk);
+    hipLaunchKernelGGL(tree_finish_kernel<kTreeSlot>, dim3(T.n_batches), dim3(kBlock), 0, s, d,
+                       0.0, 0.0, u, slot, M.st, sk);
+}
+
+int64_t tree_generation(const TreeState &T) { return T.generation; }
+
 }  // namespace gabi
 
 using namespace gabi;

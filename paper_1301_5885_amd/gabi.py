@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libgabi.so")
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ESTATE, EMESH, ENOMEM, EDEVICE, EBUSY = -1, -2, -3, -4, -5, -6
 FP64, FP32_PAIR = 0, 1
-SOLVE_FP64, SOLVE_MIXED_IR = 0, 1
+SOLVE_FP64, SOLVE_MIXED_IR, SOLVE_TREE_IR = 0, 1, 2
 SCHEME_SPLIT, SCHEME_SYMMETRIC = 0, 1
 _NAMES = {0: "GABI_OK", 1: "GABI_NOT_CONVERGED", -1: "GABI_EINVAL",
           -2: "GABI_ESTATE", -3: "GABI_EMESH", -4: "GABI_ENOMEM",
@@ -64,7 +64,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
                 ("mode", C.c_int32), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int32), ("use_graph", C.c_int32),
-                ("x0_previous", C.c_int32)]
+                ("x0_previous", C.c_int32), ("tree_theta", C.c_double),
+                ("tree_degree", C.c_int32), ("tree_leaf", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -72,7 +73,7 @@ class SolveInfo(C.Structure):
                 ("matvecs_fp32", C.c_int64), ("restarts", C.c_int64),
                 ("outer", C.c_int64), ("rel_residual", C.c_double),
                 ("converged", C.c_int32), ("seconds", C.c_double),
-                ("warm_start", C.c_int32)]
+                ("warm_start", C.c_int32), ("matvecs_tree", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

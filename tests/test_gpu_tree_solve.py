@@ -1,0 +1,130 @@
+"""GPU: the treecode refinement (GABI_SOLVE_TREE_IR): FP64 iterative
+refinement whose inner GMRES(m) cycles take their products from the
+treecode (tree.hip) while every residual is the FP64 direct product of
+Section 2.2, eqs. (eqdbef1)/(eqdbef2).  The stopping rule is the same
+explicit ||b - Au|| / ||b|| as the other solvers', so the solution is
+checked against the oracle exactly as theirs are: the tightly solved oracle
+(the stored kirkwood solve, or an oracle GMRES of a small surface), the
+energy (Section 2.3, eq. (solvation_energy)) and phi/psi (Section 3.1,
+eq. (eqerr1)).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_5885_amd import gabi
+from paper_1301_5885_amd.synth import charges_in_star, config_problem, star_surface
+
+pytestmark = pytest.mark.gpu
+EPS1, EPS2, KAPPA = 1.0, 80.0, 0.1257
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gabi.Context(0)
+    yield c
+    c.close()
+
+
+def star(nu, R, nc, seed):
+    rng = np.random.default_rng(seed)
+    V, F, shape = star_surface(nu, R, rng)
+    pos = charges_in_star(rng, shape, nc, 0.8)
+    return V, F, pos, rng.normal(0.0, 0.5, nc)
+
+
+def test_tree_ir_kirkwood_against_stored_oracle_solve(ctx):
+    """Whole kirkwood workload (N = 20,480): the energy and phi/psi over all
+    elements against the oracle's tol-1e-12 solve, to the accuracy of a
+    1e-8 solve (the mixed solver's bound: 1e-6)."""
+    p = config_problem("kirkwood")
+    ref = json.load(open(os.path.join(HERE, "golden", "kirkwood_reference.json")))
+    u_ref = np.load(os.path.join(HERE, "golden", ref["full_u"]), allow_pickle=False)
+    ctx.load_problem(p)
+    log("[tree-ir] kirkwood N=20480")
+    u, info = ctx.solve(tol=1e-8, mode=gabi.SOLVE_TREE_IR)
+    E = ctx.energy()
+    n = p.n
+    e_rel = abs(E / ref["energy_kcal_per_mol"] - 1)
+    log(f"    {info} E={E} rel={e_rel:.2e} phi {rel(u[:n], u_ref[:n]):.2e} "
+        f"psi {rel(u[n:], u_ref[n:]):.2e}")
+    assert info["converged"] and info["rel_residual"] <= 1e-8
+    assert info["matvecs_tree"] > 0 and info["matvecs_fp32"] == 0
+    assert info["matvecs_fp64"] == info["outer"]
+    assert e_rel <= 1e-6
+    assert rel(u[:n], u_ref[:n]) <= 1e-6 and rel(u[n:], u_ref[n:]) <= 1e-6
+
+
+@pytest.mark.parametrize("theta,degree,leaf", [(0.7, 5, 256), (0.5, 3, 64)])
+def test_tree_ir_small_surface_against_oracle_gmres(ctx, theta, degree, leaf):
+    """A ragged star surface (N = 4,500) solved to 1e-10 with two treecode
+    settings: the solution against the oracle's GMRES to 1e-10."""
+    V, F, pos, q = star(15, 16.0, 110, 8)
+    ctx.set_surface_mesh(V, F)
+    ctx.set_charges(pos, q)
+    ctx.set_params(EPS1, EPS2, KAPPA)
+    el = oracle.mesh_elements(V, F)
+    log(f"[tree-ir] star N={el.n} theta={theta} degree={degree} leaf={leaf}")
+    b = oracle.rhs(el, pos, q)
+    u_ref, _ = oracle.gmres(el, b, EPS1, EPS2, KAPPA, tol=1e-11, maxit=400)
+    E_ref = oracle.energy(el, u_ref, pos, q)
+    u, info = ctx.solve(tol=1e-10, maxit=400, max_outer=40, mode=gabi.SOLVE_TREE_IR,
+                        tree_theta=theta, tree_degree=degree, tree_leaf=leaf)
+    E = ctx.energy()
+    log(f"    {info} rel u {rel(u, u_ref):.2e} E rel {abs(E / E_ref - 1):.2e}")
+    assert info["converged"] and info["rel_residual"] <= 1e-10
+    assert rel(u, u_ref) <= 1e-8
+    assert abs(E / E_ref - 1) <= 1e-9
+
+
+def test_tree_ir_graph_replay_equals_eager_and_modes_alternate(ctx):
+    """The captured rounds give the eager result bit for bit; switching
+    between the mixed and the treecode refinement on one context recaptures
+    the round, so each mode's result is the same before and after."""
+    V, F, pos, q = star(12, 12.0, 60, 9)
+    ctx.set_surface_mesh(V, F)
+    ctx.set_charges(pos, q)
+    ctx.set_params(EPS1, EPS2, KAPPA)
+    log("[tree-ir] graph / eager / mode switches")
+    u_t1, i_t1 = ctx.solve(tol=1e-9, mode=gabi.SOLVE_TREE_IR)
+    u_m1, _ = ctx.solve(tol=1e-9, mode=gabi.SOLVE_MIXED_IR)
+    u_t2, i_t2 = ctx.solve(tol=1e-9, mode=gabi.SOLVE_TREE_IR)
+    u_m2, _ = ctx.solve(tol=1e-9, mode=gabi.SOLVE_MIXED_IR)
+    u_te, i_te = ctx.solve(tol=1e-9, mode=gabi.SOLVE_TREE_IR, use_graph=0)
+    log(f"    tree {i_t1['iterations']} / {i_t2['iterations']} / eager {i_te['iterations']}")
+    assert np.array_equal(u_t1, u_t2) and np.array_equal(u_m1, u_m2)
+    assert np.array_equal(u_t1, u_te)
+    # another treecode setting rebuilds the tree and still converges
+    u_t3, i_t3 = ctx.solve(tol=1e-9, mode=gabi.SOLVE_TREE_IR, tree_theta=0.4)
+    assert i_t3["converged"] and rel(u_t3, u_t1) <= 1e-7
+
+
+def test_tree_ir_for_single_contexts_only(ctx):
+    """Batches and servers reject the treecode refinement; so do bad
+    treecode options."""
+    V, F, pos, q = star(8, 8.0, 20, 10)
+    req = gabi.Request.from_mesh(V, F, pos, q, eps1=EPS1, eps2=EPS2, kappa=KAPPA, tag=0)
+    with pytest.raises(gabi.GabiError):
+        gabi.batch_solve([req], mode=gabi.SOLVE_TREE_IR)
+    with pytest.raises(gabi.GabiError):
+        gabi.Server(device=0, budget_bytes=1 << 28, max_slots=2, mode=gabi.SOLVE_TREE_IR)
+    ctx.set_surface_mesh(V, F)
+    ctx.set_charges(pos, q)
+    ctx.set_params(EPS1, EPS2, KAPPA)
+    for bad in ({"tree_theta": 1.0}, {"tree_degree": 9}, {"tree_leaf": 257}):
+        with pytest.raises(gabi.GabiError):
+            ctx.solve(tol=1e-8, mode=gabi.SOLVE_TREE_IR, **bad)
