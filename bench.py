@@ -23,6 +23,9 @@ Printed (one JSON line on stdout):
              solves) against the published FP32 vector peak; executed_frac
              is the rocprofv3 VALU FLOP count over the same time.
   fp64_solver  the plain FP64 GMRES solver on the same workload.
+  tree_ir_solver  the treecode refinement on the same workload: GMRES(10)
+             cycles on the treecode product inside FP64 refinement (solves/s,
+             errors, speedup over the mixed and FP64 solvers).
   secondary  the same figures on a smaller workload (default kirkwood).
   cpu_baseline  the FP64 CPU oracle on the host cores: product rate, an
              extrapolated solve time at the workload, a measured solve of
@@ -187,10 +190,11 @@ def run_solver(ctx, gabi, torch, u, mode, steps, warmup, event_solves, pairs):
         kt[key] = (avg, cnt)
     p64 = sum(i["matvecs_fp64"] for i in infos)
     p32 = sum(i["matvecs_fp32"] for i in infos)
+    ptree = sum(i.get("matvecs_tree", 0) for i in infos)
     return {
         "steps": steps, "elapsed": elapsed, "infos": infos, "energies": energies,
         "u": u_host,
-        "products_fp64": p64, "products_fp32": p32,
+        "products_fp64": p64, "products_fp32": p32, "products_tree": ptree,
         "gpairs_per_s": (p64 + p32) * pairs / elapsed / 1e9,
         "solves_per_s": steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
@@ -425,8 +429,11 @@ def tree_crossover(gabi, torch, nus=(16, 32, 40, 48, 56, 64, 96, 128), reps=3):
                               "measured)"}
 
 
-def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves):
-    """Mixed and FP64 solves of one workload on one context."""
+def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves, tree_steps=0):
+    """Mixed and FP64 solves of one workload on one context (and, with
+    tree_steps, the treecode refinement: inner cycles on treecode products,
+    FP64 direct residuals; its products are not direct pairs, so it reports
+    solves/s and its errors, not Gpair-kernels/s or a roofline)."""
     from paper_1301_5885_amd.synth import config_problem
     t0 = time.perf_counter()
     p = config_problem(name)
@@ -439,10 +446,13 @@ def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves):
     ref = golden(name)
     E_ref = ref["energy_kcal_per_mol"] if ref else None
     results = {}
-    for key, mode, k, w in (("mixed", gabi.SOLVE_MIXED_IR, steps, warmup),
-                            ("fp64", gabi.SOLVE_FP64, fp64_steps, min(warmup, 1))):
-        log(f"[bench] {name} {key}: {w} warmup + {k} timed + {event_solves} event-timed solves")
-        r = run_solver(ctx, gabi, torch, u, mode, k, w, event_solves, n * (n - 1))
+    runs = [("mixed", gabi.SOLVE_MIXED_IR, steps, warmup, event_solves),
+            ("fp64", gabi.SOLVE_FP64, fp64_steps, min(warmup, 1), event_solves)]
+    if tree_steps > 0:
+        runs.append(("tree_ir", gabi.SOLVE_TREE_IR, tree_steps, 1, 0))
+    for key, mode, k, w, ev in runs:
+        log(f"[bench] {name} {key}: {w} warmup + {k} timed + {ev} event-timed solves")
+        r = run_solver(ctx, gabi, torch, u, mode, k, w, ev, n * (n - 1))
         E = r["energies"][-1]
         r["energy"] = E
         r["energy_rel_err"] = abs(E / E_ref - 1) if E_ref else None
@@ -452,6 +462,7 @@ def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves):
             f"{r['gpairs_per_s']:.1f} Gpairs/s, E={E:.8f}, err={r['energy_rel_err']}, "
             f"potential {r['potential_err']}")
     mixed, fp64 = results["mixed"], results["fp64"]
+    tree = results.get("tree_ir")
     solver_line = lambda r, key: {
         "value": round(r["gpairs_per_s"], 3), "unit": "Gpair-kernels/s",
         "solves_per_s": round(r["solves_per_s"], 4), "ms_per_step": round(r["ms_per_step"], 4),
@@ -466,6 +477,20 @@ def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves):
                                 f"{ref['tol']:g})") if ref else None,
            "mixed": solver_line(mixed, "fp32"), "fp64_solver": solver_line(fp64, "fp64"),
            "speedup_mixed_over_fp64": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3)}
+    if tree:
+        out["tree_ir_solver"] = {
+            "method": "FP64 iterative refinement around GMRES(10) cycles on the treecode "
+                      "product (theta 0.7, degree 5, leaves of 256); residuals are FP64 "
+                      "direct products",
+            "solves_per_s": round(tree["solves_per_s"], 4),
+            "ms_per_step": round(tree["ms_per_step"], 4), "steps": tree["steps"],
+            "energy": tree["energy"], "energy_rel_err": tree["energy_rel_err"],
+            "potential_err": tree["potential_err"],
+            "products_per_solve": {"tree": tree["products_tree"] / tree["steps"],
+                                   "fp64": tree["products_fp64"] / tree["steps"]},
+            "speedup_over_mixed": round(tree["solves_per_s"] / mixed["solves_per_s"], 3),
+            "speedup_over_fp64": round(tree["solves_per_s"] / fp64["solves_per_s"], 3),
+            "energy_rel_diff_vs_fp64_solver": abs(tree["energy"] / fp64["energy"] - 1)}
     return ctx, p, out
 
 
@@ -478,6 +503,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3,
                     help="timed solves of the plain FP64 solver beside the headline "
                          "(at most --steps)")
+    ap.add_argument("--tree-steps", type=int, default=5,
+                    help="timed solves of the treecode refinement beside the headline "
+                         "(0: skip)")
     ap.add_argument("--event-solves", type=int, default=2,
                     help="solves with HIP events around the pair kernels (roofline)")
     ap.add_argument("--secondary", default="kirkwood",
@@ -527,7 +555,7 @@ def main():
 
     fp64_steps = max(1, min(args.fp64_steps, args.steps))
     ctx, p, head = measure(gabi, torch, args.workload, args.steps, args.warmup, fp64_steps,
-                           args.event_solves)
+                           args.event_solves, tree_steps=args.tree_steps)
     ctx.close()
     mixed = head["mixed"]
     line = {
@@ -556,10 +584,13 @@ def main():
         "fp64_solver": head["fp64_solver"],
         "speedup_mixed_over_fp64": head["speedup_mixed_over_fp64"],
     }
+    if "tree_ir_solver" in head:
+        line["tree_ir_solver"] = head["tree_ir_solver"]
     small = None
     if args.secondary != "none" and args.secondary != args.workload:
         ctx2, small, sec = measure(gabi, torch, args.secondary, args.steps, args.warmup,
-                                   args.steps, args.event_solves)
+                                   args.steps, args.event_solves,
+                                   tree_steps=args.steps if args.tree_steps > 0 else 0)
         line["secondary"] = sec
         if args.sequence_steps > 0:
             log(f"[bench] warm-started sequence: {args.sequence_steps} nearby problems")
