@@ -406,17 +406,23 @@ def tree_crossover(gabi, torch, nus=(16, 32, 40, 48, 56, 64, 96, 128), reps=3):
             t64 = timed(lambda: ctx.matvec_dev(u, y, gabi.FP64))
             t32 = timed(lambda: ctx.matvec_dev(u, yt, gabi.FP32_PAIR))
             t_tree = timed(lambda: ctx.tree_matvec_dev(u, yt, theta, degree, leaf))
+            t_tree32 = timed(lambda: ctx.tree_matvec_dev(u, yt, theta, degree, leaf,
+                                                         gabi.FP32_PAIR))
             info = ctx.tree_info(theta, degree, leaf)
             ctx.matvec_dev(u, y, gabi.FP64)
             ctx.tree_matvec_dev(u, yt, theta, degree, leaf)
             torch.cuda.synchronize()
             err = float(torch.linalg.norm(yt - y) / torch.linalg.norm(y))
+            ctx.tree_matvec_dev(u, yt, theta, degree, leaf, gabi.FP32_PAIR)
+            torch.cuda.synchronize()
+            err32 = float(torch.linalg.norm(yt - y) / torch.linalg.norm(y))
         rows.append({"N": n, "direct_fp64_ms": round(t64, 4), "direct_fp32_pair_ms": round(t32, 4),
                      "tree_fp64_ms": round(t_tree, 4), "tree_rel_err_vs_direct": err,
+                     "tree_fp32_ms": round(t_tree32, 4), "tree_fp32_rel_err_vs_direct": err32,
                      "tree_pairs_per_product": info["far_pairs"] + info["near_pairs"],
                      "tree_device_bytes": info["device_bytes"]})
         log(f"[bench] tree N={n}: direct {t64:.3f} ms (fp32-pair {t32:.3f}), tree {t_tree:.3f} "
-            f"ms, err {err:.2e}")
+            f"ms, err {err:.2e} (fp32 evaluation {t_tree32:.3f} ms, err {err32:.2e})")
     faster = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp64_ms"]]
     faster32 = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp32_pair_ms"]]
     return {"opts": {"theta": theta, "degree": degree, "leaf_size": leaf},
@@ -480,8 +486,8 @@ def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves, tree_ste
     if tree:
         out["tree_ir_solver"] = {
             "method": "FP64 iterative refinement around GMRES(10) cycles on the treecode "
-                      "product (theta 0.7, degree 5, leaves of 256); residuals are FP64 "
-                      "direct products",
+                      "product (theta 0.7, degree 5, leaves of 256, pair terms in FP32); "
+                      "residuals are FP64 direct products",
             "solves_per_s": round(tree["solves_per_s"], 4),
             "ms_per_step": round(tree["ms_per_step"], 4), "steps": tree["steps"],
             "energy": tree["energy"], "energy_rel_err": tree["energy_rel_err"],

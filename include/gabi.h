@@ -104,8 +104,9 @@ typedef struct {
                           Section 4); 0, or no such solution, starts from
                           zero.  Batch and server calls ignore it (0)         */
     double tree_theta;   /* TREE_IR: treecode options of the inner products  */
-    int32_t tree_degree; /* (gabi_tree_opts; defaults 0.7, 5, 256)            */
-    int32_t tree_leaf;
+    int32_t tree_degree; /* (gabi_tree_opts; defaults 0.7, 5, 256 and         */
+    int32_t tree_leaf;   /* GABI_FP32_PAIR: the residuals are FP64 direct      */
+    int32_t tree_precision; /* products whatever the inner precision)        */
 } gabi_solve_opts;
 
 typedef struct {
@@ -353,13 +354,19 @@ int gabi_pqr_read(const char *path, int64_t natoms, double *xyz, double *q, doub
  *     the criterion holds and it has fewer; else through its children (a
  *     leaf directly).
  * theta in [0, 1) (0: every pair directly, the exact product up to
- * summation order), degree in [1, 8], leaf_size in [1, 256]; GABI_EINVAL
- * otherwise.  The tree is built on the host at the first product after the
+ * summation order), degree in [1, 8], leaf_size in [1, 256], precision
+ * GABI_FP64 or GABI_FP32_PAIR; GABI_EINVAL otherwise.  The tree is built on the host at the first product after the
  * surface or the options change and kept on the device.                    */
 typedef struct {
     double theta;
     int32_t degree;
     int32_t leaf_size;
+    int32_t precision;  /* GABI_FP64: every pair term in FP64; GABI_FP32_PAIR:
+                           pair terms in FP32 on coordinates relative to the
+                           centre of the surface's bounding box, each staged
+                           chunk of at most 256 sources summed in FP32 and
+                           added to FP64 sums (as the FP32-pair product) */
+    int32_t reserved;   /* 0                                                 */
 } gabi_tree_opts;
 
 typedef struct {

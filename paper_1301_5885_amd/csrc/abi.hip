@@ -187,8 +187,10 @@ int opts_check(const gabi_solve_opts *in, gabi_solve_opts *o, std::string &msg) 
     }
     if (o->mode == GABI_SOLVE_TREE_IR &&
         (!(o->tree_theta >= 0.0 && o->tree_theta < 1.0) || o->tree_degree < 1 ||
-         o->tree_degree > 8 || o->tree_leaf < 1 || o->tree_leaf > kBlock)) {
-        msg = "treecode options: theta in [0, 1), degree in [1, 8], leaf in [1, 256]";
+         o->tree_degree > 8 || o->tree_leaf < 1 || o->tree_leaf > kBlock ||
+         (o->tree_precision != GABI_FP64 && o->tree_precision != GABI_FP32_PAIR))) {
+        msg = "treecode options: theta in [0, 1), degree in [1, 8], leaf in [1, 256], "
+              "precision GABI_FP64 or GABI_FP32_PAIR";
         return GABI_EINVAL;
     }
     if (o->x0_previous != 0 && o->x0_previous != 1) {
@@ -370,6 +372,7 @@ void gabi_default_opts(gabi_solve_opts *o) {
     o->tree_theta = 0.7;
     o->tree_degree = 5;
     o->tree_leaf = 256;
+    o->tree_precision = GABI_FP32_PAIR;
 }
 
 int gabi_create(gabi_ctx **out, int device) {
@@ -606,7 +609,7 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
     set_solve_targets(sl, o.tol, o.inner_tol, o.maxit);
     sl.mol.m = o.restart;
     if (tree) {
-        const gabi_tree_opts to{o.tree_theta, o.tree_degree, o.tree_leaf};
+        const gabi_tree_opts to{o.tree_theta, o.tree_degree, o.tree_leaf, o.tree_precision, 0};
         if ((rc = tree_for_solve(ctx, &to))) return rc;
     }
     if ((rc = sync_batch(ctx))) return rc;
@@ -616,10 +619,12 @@ static int solve_impl(gabi_ctx *ctx, const gabi_solve_opts *opts, const void *x0
         // recorded again
         const TreeState *tr = tree ? ctx->tree : nullptr;
         const int64_t gen = tr ? tree_generation(*tr) : -1;
-        if (b.tree != tr || b.tree_gen != gen) {
+        const bool f32 = tree && o.tree_precision == GABI_FP32_PAIR;
+        if (b.tree != tr || b.tree_gen != gen || b.tree_f32 != f32) {
             release_graph(b);
             b.tree = tr;
             b.tree_gen = gen;
+            b.tree_f32 = f32;
         }
     }
     Timer t = make_timer(ctx);

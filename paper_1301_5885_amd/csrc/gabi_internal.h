@@ -223,6 +223,7 @@ struct Batch {
     // tree the captured round was recorded with
     const struct TreeState *tree = nullptr;
     int64_t tree_gen = -1;
+    bool tree_f32 = false;  // FP32 evaluation of the treecode sums
 };
 
 int batch_build(Batch &b, hipStream_t stream, std::string &err);
@@ -237,7 +238,7 @@ int tree_for_solve(gabi_ctx *ctx, const gabi_tree_opts *o);
 // treecode sums of u (2n, element order) into slot (top at [j], bot at
 // [n + j]); with skip, nothing once M's cycle has ended
 void launch_tree_sums(const TreeState &T, hipStream_t s, const Mol &M, const double *u,
-                      double *slot, bool skip);
+                      double *slot, bool skip, bool f32);
 int64_t tree_generation(const TreeState &T);  // changes with every rebuild
 // pseudo-precision of the Arnoldi finish for a product held as one FP64
 // partial-sum slot (the treecode refinement's inner products)

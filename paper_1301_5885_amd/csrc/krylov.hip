@@ -290,7 +290,7 @@ void enqueue_round(Batch &b, hipStream_t s, const Timer *t) {
             // as the single partial slot of the Arnoldi finish
             const Mol &M = b.slots[0]->mol;
             launch_prep(b, s, GABI_FP64, j == 0 ? kPrepCycle0 : kPrepCycleJ, j, true);
-            launch_tree_sums(*b.tree, s, M, M.V + (size_t)j * 2 * M.n, M.part, true);
+            launch_tree_sums(*b.tree, s, M, M.V + (size_t)j * 2 * M.n, M.part, true, b.tree_f32);
             launch_finish(b, s, kPrecTree, kFinishDot, j, true);
         } else {
             launch_prep(b, s, prec, j == 0 ? kPrepCycle0 : kPrepCycleJ, j, true);

@@ -36,12 +36,14 @@
 // molecule's single partial-sum slot, the Arnoldi finish applies the diagonal
 // and the dot products, and every kernel returns at once once the cycle has
 // ended (the round's later steps).  The pair arithmetic is
-// the direct product's, FP64.  Every sum is taken in a fixed order, so
-// results are reproducible bit for bit.
+// the direct product's, FP64 (or, on request, FP32 as in the FP32-pair
+// product).  Every sum is taken in a fixed order, so results are
+// reproducible bit for bit.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <type_traits>
 #include <vector>
 
 #include "arnoldi.h"
@@ -75,6 +77,10 @@ struct TreeState {
     void *mem = nullptr;
     int64_t bytes = 0;
     double4 *spos = nullptr, *snrm = nullptr, *sw = nullptr, *ppos = nullptr, *pw = nullptr;
+    // FP32 copies for the FP32 evaluation: positions relative to the centre
+    // of the surface's bounding box (rounded once), normals, weights
+    float4 *spos32 = nullptr, *snrm32 = nullptr, *sw32 = nullptr, *ppos32 = nullptr,
+           *pw32 = nullptr;
     int *perm_d = nullptr;
     double *cheb = nullptr;   // 3 (n+1) nodes per cluster
     int4 *clusters = nullptr;  // (begin, end, proxy offset, 0)
@@ -227,6 +233,10 @@ int validate_tree_opts(const gabi_tree_opts *o, std::string &msg) {
         msg = "leaf_size must be in [1, " + std::to_string(kTreeMaxLeaf) + "]";
         return GABI_EINVAL;
     }
+    if (o->precision != GABI_FP64 && o->precision != GABI_FP32_PAIR) {
+        msg = "precision must be GABI_FP64 or GABI_FP32_PAIR";
+        return GABI_EINVAL;
+    }
     return GABI_OK;
 }
 
@@ -254,6 +264,8 @@ struct TreeDev {
     double4 *sw;
     const double4 *ppos;
     double4 *pw;
+    const float4 *spos32, *snrm32, *ppos32;
+    float4 *sw32, *pw32;
     const int *perm;
     const double *cheb;
     const int4 *clusters, *batches, *list, *items;
@@ -262,7 +274,9 @@ struct TreeDev {
     double bary[kTreeMaxDeg + 1];
 };
 
-// Weights of the product in tree order: s = W psi/(4 pi), m = W phi nu/(4 pi).
+// Weights of the product in tree order: s = W psi/(4 pi), m = W phi nu/(4 pi)
+// (F32: also rounded to FP32 for the FP32 evaluation).
+template <bool F32>
 __global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const double *__restrict__ u,
                                                           const KrylovStatus *st, int skip) {
     if (skip && load_done(st)) return;
@@ -272,7 +286,9 @@ __global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const doub
     const double4 q = T.spos[p], nu = T.snrm[p];
     const double c = q.w * (1.0 / (4.0 * kPi));
     const double s = c * u[T.n + j], t = c * u[j];
-    T.sw[p] = make_double4(s, t * nu.x, t * nu.y, t * nu.z);
+    const double4 w = make_double4(s, t * nu.x, t * nu.y, t * nu.z);
+    T.sw[p] = w;
+    if constexpr (F32) T.sw32[p] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)w.w);
 }
 
 // Modified weights of one proxy cluster: W_k = sum_j L_k(y_j) w_j over the
@@ -282,6 +298,7 @@ __global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const doub
 constexpr int kTreeChunk = 64;
 constexpr int kTreeProxPerThread = (729 + kBlock - 1) / kBlock;
 
+template <bool F32>
 __global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T, const KrylovStatus *st,
                                                              int skip) {
     __shared__ double s_l[3][kTreeChunk][kTreeMaxDeg + 1];
@@ -339,7 +356,12 @@ __global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T, const K
 #pragma unroll
     for (int r = 0; r < kTreeProxPerThread; ++r) {
         const int k = threadIdx.x + r * kBlock;
-        if (k < T.P) T.pw[(size_t)cl.z + k] = acc[r];
+        if (k < T.P) {
+            T.pw[(size_t)cl.z + k] = acc[r];
+            if constexpr (F32)
+                T.pw32[(size_t)cl.z + k] =
+                    make_float4((float)acc[r].x, (float)acc[r].y, (float)acc[r].z, (float)acc[r].w);
+        }
     }
 }
 
@@ -348,11 +370,16 @@ __global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T, const K
 // skipped; far: proxies).  Thread t serves target t mod P with the sources
 // j = t / P (mod G) of every staged chunk, G = 256 / P; the G sums of a
 // target are added in thread order through LDS and stored as the item's
-// partial.
+// partial.  F32: the pair terms in FP32 (the direct product's pair_f32, on
+// coordinates relative to the centre of the surface's bounding box), each
+// staged chunk summed in FP32 and added to FP64 sums.
+template <bool F32>
 __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF64 pc,
+                                                          PairConstF32 pc32,
                                                           const KrylovStatus *st, int skip) {
-    __shared__ double4 s_pos[kBlock];
-    __shared__ double4 s_w[kBlock];
+    using V4 = typename std::conditional<F32, float4, double4>::type;
+    __shared__ V4 s_pos[kBlock];
+    __shared__ V4 s_w[kBlock];
     __shared__ double2 s_sum[kBlock];
     if (skip && load_done(st)) return;
     const int4 item = T.items[blockIdx.x];
@@ -365,13 +392,26 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
     const int p = bt.x + tg;
     const bool act = tg < bsz;
     const int pc_ = act ? p : bt.x;
-    const double4 x = T.spos[pc_], nu = T.snrm[pc_];
+    V4 x, nu;
+    if constexpr (F32) {
+        x = T.spos32[pc_];
+        nu = T.snrm32[pc_];
+    } else {
+        x = T.spos[pc_];
+        nu = T.snrm[pc_];
+    }
     double top = 0.0, bot = 0.0;
     for (int e = item.y; e < item.z; ++e) {
         const int4 it = T.list[e];
         const bool far = it.x == 1;
-        const double4 *src_p = far ? T.ppos : T.spos;
-        const double4 *src_w = far ? T.pw : T.sw;
+        const V4 *src_p, *src_w;
+        if constexpr (F32) {
+            src_p = far ? T.ppos32 : T.spos32;
+            src_w = far ? T.pw32 : T.sw32;
+        } else {
+            src_p = far ? T.ppos : T.spos;
+            src_w = far ? T.pw : T.sw;
+        }
         for (int j0 = it.y; j0 < it.z; j0 += kBlock) {
             const int cnt = min(kBlock, it.z - j0);
             __syncthreads();
@@ -381,11 +421,23 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
             }
             __syncthreads();
             const bool self = !far && j0 < bt.y && j0 + cnt > bt.x;
-            for (int jj = grp; jj < cnt; jj += G) {
-                if (self && j0 + jj == p) continue;
-                const double4 q = s_pos[jj], w = s_w[jj];
-                pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
-                         w.w, top, bot);
+            if constexpr (F32) {
+                float t32 = 0.0f, b32 = 0.0f;
+                for (int jj = grp; jj < cnt; jj += G) {
+                    if (self && j0 + jj == p) continue;
+                    const float4 q = s_pos[jj], w = s_w[jj];
+                    pair_f32(pc32, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
+                             w.w, t32, b32);
+                }
+                top += (double)t32;
+                bot += (double)b32;
+            } else {
+                for (int jj = grp; jj < cnt; jj += G) {
+                    if (self && j0 + jj == p) continue;
+                    const double4 q = s_pos[jj], w = s_w[jj];
+                    pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
+                             w.w, top, bot);
+                }
             }
         }
     }
@@ -489,6 +541,19 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
         spos[(size_t)p] = pos[T.perm[(size_t)p]];
         snrm[(size_t)p] = nrm[T.perm[(size_t)p]];
     }
+    // centre of the bounding box (the FP32 copies are relative to it)
+    double cen[3];
+    {
+        const TreeNode &R = T.nodes[0];
+        for (int d = 0; d < 3; ++d) cen[d] = (R.lo[d] + R.hi[d]) / 2.0;
+    }
+    std::vector<float4> spos32((size_t)n), snrm32((size_t)n);
+    for (int64_t p = 0; p < n; ++p) {
+        const double4 a = spos[(size_t)p], b = snrm[(size_t)p];
+        spos32[(size_t)p] = make_float4((float)(a.x - cen[0]), (float)(a.y - cen[1]),
+                                        (float)(a.z - cen[2]), 0.0f);
+        snrm32[(size_t)p] = make_float4((float)b.x, (float)b.y, (float)b.z, 0.0f);
+    }
     const int nc = T.n_clusters;
     std::vector<double> cheb((size_t)nc * 3 * np1);
     std::vector<int4> clusters((size_t)nc);
@@ -504,6 +569,10 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
                 make_double4(cn[k1], cn[np1 + k2], cn[2 * np1 + k3], 0.0);
         }
     }
+    std::vector<float4> ppos32(ppos.size());
+    for (size_t k = 0; k < ppos.size(); ++k)
+        ppos32[k] = make_float4((float)(ppos[k].x - cen[0]), (float)(ppos[k].y - cen[1]),
+                                (float)(ppos[k].z - cen[2]), 0.0f);
     std::vector<int4> batches(batch_nodes.size()), list, items;
     int64_t total_src = 0;
     for (size_t b = 0; b < batch_nodes.size(); ++b)
@@ -552,7 +621,13 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     const int64_t o_li = al(o_bt + 16 * (int64_t)batches.size());
     const int64_t o_it = al(o_li + 16 * std::max<int64_t>(1, (int64_t)list.size()));
     const int64_t o_ip = al(o_it + 16 * (int64_t)items.size());
-    const int64_t total = al(o_ip + 16 * (int64_t)kBlock * (int64_t)items.size());
+    const int64_t np_ = std::max<int64_t>(1, (int64_t)ppos.size());
+    const int64_t o_sp32 = al(o_ip + 16 * (int64_t)kBlock * (int64_t)items.size());
+    const int64_t o_sn32 = al(o_sp32 + 16 * n);
+    const int64_t o_sw32 = al(o_sn32 + 16 * n);
+    const int64_t o_pp32 = al(o_sw32 + 16 * n);
+    const int64_t o_pw32 = al(o_pp32 + 16 * np_);
+    const int64_t total = al(o_pw32 + 16 * np_);
     if (ctx->stream) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (T.mem) (void)hipFree(T.mem);
     T.mem = nullptr;
@@ -577,6 +652,11 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     T.list = reinterpret_cast<int4 *>(base + o_li);
     T.items = reinterpret_cast<int4 *>(base + o_it);
     T.ipart = reinterpret_cast<double2 *>(base + o_ip);
+    T.spos32 = reinterpret_cast<float4 *>(base + o_sp32);
+    T.snrm32 = reinterpret_cast<float4 *>(base + o_sn32);
+    T.sw32 = reinterpret_cast<float4 *>(base + o_sw32);
+    T.ppos32 = reinterpret_cast<float4 *>(base + o_pp32);
+    T.pw32 = reinterpret_cast<float4 *>(base + o_pw32);
     auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream)
                      : hipSuccess;
@@ -590,6 +670,9 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     GABI_HIP(ctx, up(T.batches, batches.data(), 16 * batches.size()));
     GABI_HIP(ctx, up(T.list, list.data(), 16 * list.size()));
     GABI_HIP(ctx, up(T.items, items.data(), 16 * items.size()));
+    GABI_HIP(ctx, up(T.spos32, spos32.data(), 16 * (size_t)n));
+    GABI_HIP(ctx, up(T.snrm32, snrm32.data(), 16 * (size_t)n));
+    GABI_HIP(ctx, up(T.ppos32, ppos32.data(), 16 * ppos32.size()));
     GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
     T.version = ctx->geom_version;
     ++T.generation;
@@ -613,11 +696,43 @@ TreeDev tree_dev(const TreeState &T) {
     d.list = T.list;
     d.items = T.items;
     d.ipart = T.ipart;
+    d.spos32 = T.spos32;
+    d.snrm32 = T.snrm32;
+    d.ppos32 = T.ppos32;
+    d.sw32 = T.sw32;
+    d.pw32 = T.pw32;
     d.n = T.n;
     d.degree = T.degree;
     d.P = T.P;
     for (int k = 0; k <= kTreeMaxDeg; ++k) d.bary[k] = T.bary[k];
     return d;
+}
+
+// prep, modified weights and sums of one product in the given precision
+void launch_tree_sums3(const TreeState &T, const TreeDev &d, hipStream_t s, bool f32,
+                       const PairConstF64 &pc, const PairConstF32 &pc32, const double *u,
+                       const KrylovStatus *st, int skip) {
+    const dim3 gp((T.n + kBlock - 1) / kBlock), blk(kBlock);
+    if (f32) {
+        hipLaunchKernelGGL(tree_prep_kernel<true>, gp, blk, 0, s, d, u, st, skip);
+        if (T.n_clusters > 0)
+            hipLaunchKernelGGL(tree_weights_kernel<true>, dim3(T.n_clusters), blk, 0, s, d, st,
+                               skip);
+        hipLaunchKernelGGL(tree_eval_kernel<true>, dim3(T.n_items), blk, 0, s, d, pc, pc32, st,
+                           skip);
+    } else {
+        hipLaunchKernelGGL(tree_prep_kernel<false>, gp, blk, 0, s, d, u, st, skip);
+        if (T.n_clusters > 0)
+            hipLaunchKernelGGL(tree_weights_kernel<false>, dim3(T.n_clusters), blk, 0, s, d, st,
+                               skip);
+        hipLaunchKernelGGL(tree_eval_kernel<false>, dim3(T.n_items), blk, 0, s, d, pc, pc32, st,
+                           skip);
+    }
+}
+
+PairConstF32 pair_const_f32(double kappa, double eps) {
+    return PairConstF32{(float)kappa, (float)(-kappa * 1.4426950408889634074), (float)eps,
+                        (float)(1.0 / eps)};
 }
 
 int tree_product(gabi_ctx *ctx, const gabi_tree_opts *o, const double *u_dev, double *y_dev) {
@@ -636,13 +751,8 @@ int tree_product(gabi_ctx *ctx, const gabi_tree_opts *o, const double *u_dev, do
         }
         if (e0) (void)hipEventRecord(e0, ctx->stream);
     }
-    hipLaunchKernelGGL(tree_prep_kernel, dim3((T.n + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       ctx->stream, d, u_dev, nullptr, 0);
-    if (T.n_clusters > 0)
-        hipLaunchKernelGGL(tree_weights_kernel, dim3(T.n_clusters), dim3(kBlock), 0, ctx->stream,
-                           d, nullptr, 0);
-    hipLaunchKernelGGL(tree_eval_kernel, dim3(T.n_items), dim3(kBlock), 0, ctx->stream, d, pc,
-                       nullptr, 0);
+    launch_tree_sums3(T, d, ctx->stream, o->precision == GABI_FP32_PAIR, pc,
+                      pair_const_f32(ctx->kappa, eps), u_dev, nullptr, 0);
     hipLaunchKernelGGL(tree_finish_kernel<kTreeY>, dim3(T.n_batches), dim3(kBlock), 0,
                        ctx->stream, d, 0.5 * (1.0 + eps), 0.5 * (1.0 + 1.0 / eps), u_dev, y_dev,
                        nullptr, 0);
@@ -659,16 +769,12 @@ int tree_product(gabi_ctx *ctx, const gabi_tree_opts *o, const double *u_dev, do
 int tree_for_solve(gabi_ctx *ctx, const gabi_tree_opts *o) { return tree_ensure(ctx, o); }
 
 void launch_tree_sums(const TreeState &T, hipStream_t s, const Mol &M, const double *u,
-                      double *slot, bool skip) {
+                      double *slot, bool skip, bool f32) {
     const TreeDev d = tree_dev(T);
     const PairConstF64 pc{M.kappa, M.eps, M.inv_eps};
+    const PairConstF32 pc32{M.kappa_f, M.nkl2e_f, M.eps_f, M.inv_eps_f};
     const int sk = skip ? 1 : 0;
-    hipLaunchKernelGGL(tree_prep_kernel, dim3((T.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       d, u, M.st, sk);
-    if (T.n_clusters > 0)
-        hipLaunchKernelGGL(tree_weights_kernel, dim3(T.n_clusters), dim3(kBlock), 0, s, d, M.st,
-                           sk);
-    hipLaunchKernelGGL(tree_eval_kernel, dim3(T.n_items), dim3(kBlock), 0, s, d, pc, M.st, sk);
+    launch_tree_sums3(T, d, s, f32, pc, pc32, u, M.st, sk);
     hipLaunchKernelGGL(tree_finish_kernel<kTreeSlot>, dim3(T.n_batches), dim3(kBlock), 0, s, d,
                        0.0, 0.0, u, slot, M.st, sk);
 }

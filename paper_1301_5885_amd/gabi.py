@@ -65,7 +65,8 @@ class SolveOpts(C.Structure):
                 ("mode", C.c_int32), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int32), ("use_graph", C.c_int32),
                 ("x0_previous", C.c_int32), ("tree_theta", C.c_double),
-                ("tree_degree", C.c_int32), ("tree_leaf", C.c_int32)]
+                ("tree_degree", C.c_int32), ("tree_leaf", C.c_int32),
+                ("tree_precision", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -100,7 +101,8 @@ class ResultC(C.Structure):
 
 
 class TreeOpts(C.Structure):
-    _fields_ = [("theta", C.c_double), ("degree", C.c_int32), ("leaf_size", C.c_int32)]
+    _fields_ = [("theta", C.c_double), ("degree", C.c_int32), ("leaf_size", C.c_int32),
+                ("precision", C.c_int32), ("reserved", C.c_int32)]
 
 
 class TreeInfo(C.Structure):
@@ -112,8 +114,9 @@ class TreeInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-def tree_opts(theta=0.7, degree=5, leaf_size=256):
-    return TreeOpts(float(theta), int(degree), int(leaf_size))
+def tree_opts(theta=0.7, degree=5, leaf_size=256, precision=0):
+    """gabi_tree_opts; precision FP64 (0) or FP32_PAIR (1)."""
+    return TreeOpts(float(theta), int(degree), int(leaf_size), int(precision), 0)
 
 
 class ServerStats(C.Structure):
@@ -555,17 +558,17 @@ class Context:
         return e.value
 
     # -- treecode product
-    def tree_matvec(self, u, theta=0.7, degree=5, leaf_size=256):
-        o = tree_opts(theta, degree, leaf_size)
+    def tree_matvec(self, u, theta=0.7, degree=5, leaf_size=256, precision=0):
+        o = tree_opts(theta, degree, leaf_size, precision)
         ua = _f64(u)
         y = np.empty(2 * self.n)
         self._check(self._lib.gabi_tree_matvec(self._h, C.byref(o), _p(ua), _p(y)),
                     "gabi_tree_matvec")
         return y
 
-    def tree_matvec_dev(self, u, y, theta=0.7, degree=5, leaf_size=256):
+    def tree_matvec_dev(self, u, y, theta=0.7, degree=5, leaf_size=256, precision=0):
         self.set_stream()
-        o = tree_opts(theta, degree, leaf_size)
+        o = tree_opts(theta, degree, leaf_size, precision)
         self._check(self._lib.gabi_tree_matvec_dev(self._h, C.byref(o),
                                                    _torch_ptr(u, 2 * self.n, "u"),
                                                    _torch_ptr(y, 2 * self.n, "y")),

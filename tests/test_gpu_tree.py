@@ -127,3 +127,26 @@ def test_tree_full_size_against_direct(ctx):
     err = rel(y, ctx.matvec(u, gabi.FP64))
     log(f"[tree full size] N={el.n} err vs direct {err:.2e} {ctx.tree_info(0.7, 5, 256)}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("theta,degree,leaf", [(0.7, 5, 256), (0.5, 3, 64)])
+@pytest.mark.parametrize("name", ["sphere_5120", "star_2880"])
+def test_tree_fp32_evaluation(ctx, name, theta, degree, leaf):
+    """The FP32 evaluation of the treecode sums (precision GABI_FP32_PAIR):
+    the same tree and lists, pair terms in FP32 on centred coordinates.
+    Against the FP64 treecode product of the same options within the
+    FP32-pair product's bound (max(2e-6, 2^-24 L/h), L the largest centred
+    coordinate, h the element size), and repeatable bit for bit."""
+    from test_gpu_parity import fp32_tol
+    V, F = surface(name)
+    el = load(ctx, V, F)
+    u = np.random.default_rng(el.n + 17).normal(size=2 * el.n)
+    y64 = ctx.tree_matvec(u, theta, degree, leaf)
+    y32 = ctx.tree_matvec(u, theta, degree, leaf, precision=gabi.FP32_PAIR)
+    tol = fp32_tol(el)
+    log(f"[tree fp32] {name} theta={theta} degree={degree} leaf={leaf}: "
+        f"{rel(y32, y64):.2e} max {relmax(y32, y64):.2e} (tol {tol:.1e})")
+    assert rel(y32, y64) <= tol and relmax(y32, y64) <= tol
+    assert np.array_equal(y32, ctx.tree_matvec(u, theta, degree, leaf, precision=gabi.FP32_PAIR))
+    with pytest.raises(gabi.GabiError):
+        ctx.tree_matvec(u, theta, degree, leaf, precision=7)

@@ -1,7 +1,8 @@
 """GPU: the treecode refinement (GABI_SOLVE_TREE_IR): FP64 iterative
 refinement whose inner GMRES(m) cycles take their products from the
 treecode (tree.hip) while every residual is the FP64 direct product of
-Section 2.2, eqs. (eqdbef1)/(eqdbef2).  The stopping rule is the same
+Section 2.2, eqs. (eqdbef1)/(eqdbef2) (the treecode sums in FP32 by
+default, in FP64 on request).  The stopping rule is the same
 explicit ||b - Au|| / ||b|| as the other solvers', so the solution is
 checked against the oracle exactly as theirs are: the tightly solved oracle
 (the stored kirkwood solve, or an oracle GMRES of a small surface), the
@@ -69,10 +70,12 @@ def test_tree_ir_kirkwood_against_stored_oracle_solve(ctx):
     assert rel(u[:n], u_ref[:n]) <= 1e-6 and rel(u[n:], u_ref[n:]) <= 1e-6
 
 
-@pytest.mark.parametrize("theta,degree,leaf", [(0.7, 5, 256), (0.5, 3, 64)])
-def test_tree_ir_small_surface_against_oracle_gmres(ctx, theta, degree, leaf):
+@pytest.mark.parametrize("theta,degree,leaf,prec", [(0.7, 5, 256, 1), (0.5, 3, 64, 1),
+                                                    (0.7, 5, 256, 0)])
+def test_tree_ir_small_surface_against_oracle_gmres(ctx, theta, degree, leaf, prec):
     """A ragged star surface (N = 4,500) solved to 1e-10 with two treecode
-    settings: the solution against the oracle's GMRES to 1e-10."""
+    settings and both evaluation precisions: the solution against the
+    oracle's GMRES to 1e-10."""
     V, F, pos, q = star(15, 16.0, 110, 8)
     ctx.set_surface_mesh(V, F)
     ctx.set_charges(pos, q)
@@ -83,7 +86,8 @@ def test_tree_ir_small_surface_against_oracle_gmres(ctx, theta, degree, leaf):
     u_ref, _ = oracle.gmres(el, b, EPS1, EPS2, KAPPA, tol=1e-11, maxit=400)
     E_ref = oracle.energy(el, u_ref, pos, q)
     u, info = ctx.solve(tol=1e-10, maxit=400, max_outer=40, mode=gabi.SOLVE_TREE_IR,
-                        tree_theta=theta, tree_degree=degree, tree_leaf=leaf)
+                        tree_theta=theta, tree_degree=degree, tree_leaf=leaf,
+                        tree_precision=prec)
     E = ctx.energy()
     log(f"    {info} rel u {rel(u, u_ref):.2e} E rel {abs(E / E_ref - 1):.2e}")
     assert info["converged"] and info["rel_residual"] <= 1e-10
@@ -108,9 +112,14 @@ def test_tree_ir_graph_replay_equals_eager_and_modes_alternate(ctx):
     log(f"    tree {i_t1['iterations']} / {i_t2['iterations']} / eager {i_te['iterations']}")
     assert np.array_equal(u_t1, u_t2) and np.array_equal(u_m1, u_m2)
     assert np.array_equal(u_t1, u_te)
-    # another treecode setting rebuilds the tree and still converges
+    # another treecode setting rebuilds the tree and still converges; so does
+    # the FP64 evaluation of the inner products (the default is FP32)
     u_t3, i_t3 = ctx.solve(tol=1e-9, mode=gabi.SOLVE_TREE_IR, tree_theta=0.4)
     assert i_t3["converged"] and rel(u_t3, u_t1) <= 1e-7
+    u_t4, i_t4 = ctx.solve(tol=1e-9, mode=gabi.SOLVE_TREE_IR, tree_precision=gabi.FP64)
+    assert i_t4["converged"] and rel(u_t4, u_t1) <= 1e-7
+    u_t5, _ = ctx.solve(tol=1e-9, mode=gabi.SOLVE_TREE_IR)
+    assert np.array_equal(u_t5, u_t1)
 
 
 def test_tree_ir_for_single_contexts_only(ctx):
@@ -125,6 +134,7 @@ def test_tree_ir_for_single_contexts_only(ctx):
     ctx.set_surface_mesh(V, F)
     ctx.set_charges(pos, q)
     ctx.set_params(EPS1, EPS2, KAPPA)
-    for bad in ({"tree_theta": 1.0}, {"tree_degree": 9}, {"tree_leaf": 257}):
+    for bad in ({"tree_theta": 1.0}, {"tree_degree": 9}, {"tree_leaf": 257},
+                {"tree_precision": 5}):
         with pytest.raises(gabi.GabiError):
             ctx.solve(tol=1e-8, mode=gabi.SOLVE_TREE_IR, **bad)
