@@ -22,9 +22,11 @@
 //    directly when it has at most P elements), else a leaf acts directly and
 //    an inner node hands over to its children.
 //
-// Per product four kernels run: weights in tree order (tree_prep), the
-// modified weights (tree_weights, one workgroup per proxy cluster), the
-// sums (tree_eval) and their reduction (tree_finish).  A batch's interaction
+// Per product five kernels run: weights in tree order (tree_prep), the
+// modified weights of every proxy cluster in pieces of at most 2,048
+// elements (tree_weights, one workgroup per piece, so that the largest
+// clusters do not serialise the launch) and their sum in piece order
+// (tree_wsum), the sums (tree_eval) and their reduction (tree_finish).  A batch's interaction
 // list is cut into work items of a bounded number of sources, one workgroup
 // each: the item's sources are staged through LDS 256 records at a time and
 // every target of the batch is served by 256/P threads (P the batch size
@@ -83,12 +85,15 @@ struct TreeState {
            *pw32 = nullptr;
     int *perm_d = nullptr;
     double *cheb = nullptr;   // 3 (n+1) nodes per cluster
-    int4 *clusters = nullptr;  // (begin, end, proxy offset, 0)
+    int4 *clusters = nullptr;  // (begin, end, proxy offset, first piece)
     int4 *batches = nullptr;   // (begin, end, first item, item count)
     int4 *list = nullptr;      // (0 near | 1 far, begin, end, 0)
     int4 *items = nullptr;     // (batch, list begin, list end, 0)
     double2 *ipart = nullptr;  // [item][kBlock] partial (top, bot) per target
     int n_items = 0;
+    int4 *pieces = nullptr;    // (cluster, element begin, element end, 0)
+    double4 *wpart = nullptr;  // [piece][P] partial modified weights
+    int n_pieces = 0;
     int64_t generation = 0;  // counts rebuilds (captured rounds compare it)
 };
 
@@ -268,8 +273,9 @@ struct TreeDev {
     float4 *sw32, *pw32;
     const int *perm;
     const double *cheb;
-    const int4 *clusters, *batches, *list, *items;
+    const int4 *clusters, *batches, *list, *items, *pieces;
     double2 *ipart;
+    double4 *wpart;
     int n, degree, P;
     double bary[kTreeMaxDeg + 1];
 };
@@ -291,27 +297,28 @@ __global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const doub
     if constexpr (F32) T.sw32[p] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)w.w);
 }
 
-// Modified weights of one proxy cluster: W_k = sum_j L_k(y_j) w_j over the
-// cluster's elements in tree order.  The 1-D bases of 64 elements are formed
-// at a time (one (element, dimension) per thread), then each thread adds the
-// chunk's terms to its proxies k = tid, tid + 256, ...
+// Partial modified weights of one piece (at most kTreePiece elements) of a
+// proxy cluster: W_k = sum_j L_k(y_j) w_j over the piece's elements in tree
+// order.  The 1-D bases of 64 elements are formed at a time (one (element,
+// dimension) per thread), then each thread adds the chunk's terms to its
+// proxies k = tid, tid + 256, ...
 constexpr int kTreeChunk = 64;
 constexpr int kTreeProxPerThread = (729 + kBlock - 1) / kBlock;
+constexpr int kTreePiece = 2048;  // elements per workgroup of the modified weights
 
-template <bool F32>
 __global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T, const KrylovStatus *st,
                                                              int skip) {
     __shared__ double s_l[3][kTreeChunk][kTreeMaxDeg + 1];
     __shared__ double4 s_w[kTreeChunk];
     if (skip && load_done(st)) return;
-    const int4 cl = T.clusters[blockIdx.x];
+    const int4 pc = T.pieces[blockIdx.x];
     const int deg = T.degree, np1 = deg + 1;
-    const double *nodes = T.cheb + (size_t)blockIdx.x * 3 * np1;
+    const double *nodes = T.cheb + (size_t)pc.x * 3 * np1;
     double4 acc[kTreeProxPerThread];
 #pragma unroll
     for (int r = 0; r < kTreeProxPerThread; ++r) acc[r] = make_double4(0.0, 0.0, 0.0, 0.0);
-    for (int c0 = cl.x; c0 < cl.y; c0 += kTreeChunk) {
-        const int cnt = min(kTreeChunk, cl.y - c0);
+    for (int c0 = pc.y; c0 < pc.z; c0 += kTreeChunk) {
+        const int cnt = min(kTreeChunk, pc.z - c0);
         __syncthreads();
         if (threadIdx.x < 3 * kTreeChunk) {
             const int e = threadIdx.x / 3, d = threadIdx.x % 3;
@@ -356,13 +363,30 @@ __global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T, const K
 #pragma unroll
     for (int r = 0; r < kTreeProxPerThread; ++r) {
         const int k = threadIdx.x + r * kBlock;
-        if (k < T.P) {
-            T.pw[(size_t)cl.z + k] = acc[r];
-            if constexpr (F32)
-                T.pw32[(size_t)cl.z + k] =
-                    make_float4((float)acc[r].x, (float)acc[r].y, (float)acc[r].z, (float)acc[r].w);
-        }
+        if (k < T.P) T.wpart[(size_t)blockIdx.x * T.P + k] = acc[r];
     }
+}
+
+// Modified weights of one proxy cluster: its pieces' partials added in piece
+// order (F32: also rounded to FP32).
+template <bool F32>
+__global__ __launch_bounds__(kBlock) void tree_wsum_kernel(TreeDev T, const KrylovStatus *st,
+                                                          int skip) {
+    if (skip && load_done(st)) return;
+    const int4 cl = T.clusters[blockIdx.x];
+    const int k = (int)(blockIdx.y * kBlock + threadIdx.x);
+    if (k >= T.P) return;
+    const int count = (cl.y - cl.x + kTreePiece - 1) / kTreePiece;
+    double4 a = T.wpart[(size_t)cl.w * T.P + k];
+    for (int q = 1; q < count; ++q) {
+        const double4 v = T.wpart[(size_t)(cl.w + q) * T.P + k];
+        a.x += v.x;
+        a.y += v.y;
+        a.z += v.z;
+        a.w += v.w;
+    }
+    T.pw[(size_t)cl.z + k] = a;
+    if constexpr (F32) T.pw32[(size_t)cl.z + k] = make_float4((float)a.x, (float)a.y, (float)a.z, (float)a.w);
 }
 
 // The sums of one work item: the batch's targets against the sources of its
@@ -569,6 +593,15 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
                 make_double4(cn[k1], cn[np1 + k2], cn[2 * np1 + k3], 0.0);
         }
     }
+    // pieces of at most kTreePiece elements per proxy cluster, in cluster
+    // order, so that large clusters spread over many workgroups
+    std::vector<int4> pieces;
+    for (int c = 0; c < nc; ++c) {
+        clusters[(size_t)c].w = (int)pieces.size();
+        for (int b0 = clusters[(size_t)c].x; b0 < clusters[(size_t)c].y; b0 += kTreePiece)
+            pieces.push_back(make_int4(c, b0, std::min(b0 + kTreePiece, clusters[(size_t)c].y), 0));
+    }
+    T.n_pieces = (int)pieces.size();
     std::vector<float4> ppos32(ppos.size());
     for (size_t k = 0; k < ppos.size(); ++k)
         ppos32[k] = make_float4((float)(ppos[k].x - cen[0]), (float)(ppos[k].y - cen[1]),
@@ -627,7 +660,9 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     const int64_t o_sw32 = al(o_sn32 + 16 * n);
     const int64_t o_pp32 = al(o_sw32 + 16 * n);
     const int64_t o_pw32 = al(o_pp32 + 16 * np_);
-    const int64_t total = al(o_pw32 + 16 * np_);
+    const int64_t o_pc = al(o_pw32 + 16 * np_);
+    const int64_t o_wp = al(o_pc + 16 * std::max<int64_t>(1, (int64_t)pieces.size()));
+    const int64_t total = al(o_wp + 32 * (int64_t)T.P * std::max<int64_t>(1, (int64_t)pieces.size()));
     if (ctx->stream) GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (T.mem) (void)hipFree(T.mem);
     T.mem = nullptr;
@@ -657,6 +692,8 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     T.sw32 = reinterpret_cast<float4 *>(base + o_sw32);
     T.ppos32 = reinterpret_cast<float4 *>(base + o_pp32);
     T.pw32 = reinterpret_cast<float4 *>(base + o_pw32);
+    T.pieces = reinterpret_cast<int4 *>(base + o_pc);
+    T.wpart = reinterpret_cast<double4 *>(base + o_wp);
     auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream)
                      : hipSuccess;
@@ -673,6 +710,7 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
     GABI_HIP(ctx, up(T.spos32, spos32.data(), 16 * (size_t)n));
     GABI_HIP(ctx, up(T.snrm32, snrm32.data(), 16 * (size_t)n));
     GABI_HIP(ctx, up(T.ppos32, ppos32.data(), 16 * ppos32.size()));
+    GABI_HIP(ctx, up(T.pieces, pieces.data(), 16 * pieces.size()));
     GABI_HIP(ctx, hipStreamSynchronize(ctx->stream));
     T.version = ctx->geom_version;
     ++T.generation;
@@ -696,6 +734,8 @@ TreeDev tree_dev(const TreeState &T) {
     d.list = T.list;
     d.items = T.items;
     d.ipart = T.ipart;
+    d.pieces = T.pieces;
+    d.wpart = T.wpart;
     d.spos32 = T.spos32;
     d.snrm32 = T.snrm32;
     d.ppos32 = T.ppos32;
@@ -713,18 +753,21 @@ void launch_tree_sums3(const TreeState &T, const TreeDev &d, hipStream_t s, bool
                        const PairConstF64 &pc, const PairConstF32 &pc32, const double *u,
                        const KrylovStatus *st, int skip) {
     const dim3 gp((T.n + kBlock - 1) / kBlock), blk(kBlock);
+    const dim3 gs(T.n_clusters, (T.P + kBlock - 1) / kBlock);
     if (f32) {
         hipLaunchKernelGGL(tree_prep_kernel<true>, gp, blk, 0, s, d, u, st, skip);
-        if (T.n_clusters > 0)
-            hipLaunchKernelGGL(tree_weights_kernel<true>, dim3(T.n_clusters), blk, 0, s, d, st,
-                               skip);
+        if (T.n_clusters > 0) {
+            hipLaunchKernelGGL(tree_weights_kernel, dim3(T.n_pieces), blk, 0, s, d, st, skip);
+            hipLaunchKernelGGL(tree_wsum_kernel<true>, gs, blk, 0, s, d, st, skip);
+        }
         hipLaunchKernelGGL(tree_eval_kernel<true>, dim3(T.n_items), blk, 0, s, d, pc, pc32, st,
                            skip);
     } else {
         hipLaunchKernelGGL(tree_prep_kernel<false>, gp, blk, 0, s, d, u, st, skip);
-        if (T.n_clusters > 0)
-            hipLaunchKernelGGL(tree_weights_kernel<false>, dim3(T.n_clusters), blk, 0, s, d, st,
-                               skip);
+        if (T.n_clusters > 0) {
+            hipLaunchKernelGGL(tree_weights_kernel, dim3(T.n_pieces), blk, 0, s, d, st, skip);
+            hipLaunchKernelGGL(tree_wsum_kernel<false>, gs, blk, 0, s, d, st, skip);
+        }
         hipLaunchKernelGGL(tree_eval_kernel<false>, dim3(T.n_items), blk, 0, s, d, pc, pc32, st,
                            skip);
     }
