@@ -2,7 +2,7 @@
 """Benchmark of the boundary-integral Poisson-Boltzmann hot path on one GPU.
 
 One step = one complete solve of the workload through the C ABI: source
-terms (Eq_Ss), restarted GMRES(10) on the direct-sum product
+terms (Eq_Ss), restarted GMRES(20) on the direct-sum product
 (eqdbef1)/(eqdbef2), and the solvation energy (solvation_energy), with the
 inputs already resident on the device.  The headline solver is FP64
 iterative refinement around FP32-pair GMRES cycles; the plain FP64 GMRES
@@ -23,7 +23,7 @@ Printed (one JSON line on stdout):
              solves) against the published FP32 vector peak; executed_frac
              is the rocprofv3 VALU FLOP count over the same time.
   fp64_solver  the plain FP64 GMRES solver on the same workload.
-  tree_ir_solver  the treecode refinement on the same workload: GMRES(10)
+  tree_ir_solver  the treecode refinement on the same workload: GMRES(20)
              cycles on the treecode product inside FP64 refinement (solves/s,
              errors, speedup over the mixed and FP64 solvers).
   secondary  the same figures on a smaller workload (default kirkwood).
@@ -54,16 +54,17 @@ METRIC = "matvec Gpair-kernels/s + solves/s, mixed vs FP64 at <=1e-6 energy rel 
 FLOP_PER_PAIR = 61          # algorithmic count per ordered pair, FMA = 2
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector peaks
 TOL = 1e-8                  # relative residual of every timed solve
+RESTART = 20                # GMRES(m) of every solver: the top of Section 2.4's 10-20
 WORKLOADS = {
     "kirkwood": "Kirkwood sphere: R=20 A, geodesic nu=32 (N=20480 flat triangles), "
                 "Nc=200 charges uniform in r<=18 A, Q in {-1,+1}; eps1=1, eps2=80, "
-                "kappa=0.1257/A; GMRES(10) to rel. residual 1e-8",
+                "kappa=0.1257/A; GMRES(20) to rel. residual 1e-8",
     "star": "Star-shaped surface R=30 A, nu=64 (N=81920), Nc=2000, Q~N(0,0.5^2); "
-            "eps1=1, eps2=80, kappa=0.1257/A; GMRES(10) to rel. residual 1e-8",
+            "eps1=1, eps2=80, kappa=0.1257/A; GMRES(20) to rel. residual 1e-8",
     "born": "Born ion: sphere R=2 A, nu=8 (N=1280), one +1 charge at the centre; "
-            "eps1=1, eps2=80, kappa=0.1257/A; GMRES(10) to rel. residual 1e-8",
+            "eps1=1, eps2=80, kappa=0.1257/A; GMRES(20) to rel. residual 1e-8",
     "large": "Large single solve: sphere R=40 A, nu=128 (N=327680), Nc=5000 charges in "
-             "r<=36 A, Q~N(0,0.5^2); eps1=1, eps2=80, kappa=0.1257/A; GMRES(10) to rel. "
+             "r<=36 A, Q~N(0,0.5^2); eps1=1, eps2=80, kappa=0.1257/A; GMRES(20) to rel. "
              "residual 1e-8",
 }
 
@@ -161,13 +162,13 @@ def run_solver(ctx, gabi, torch, u, mode, steps, warmup, event_solves, pairs):
     (event-record nodes inside the replayed round graphs, about 3 us per
     record) give the kernel durations for the roofline."""
     for _ in range(warmup):
-        ctx.solve_dev(u, tol=TOL, mode=mode)
+        ctx.solve_dev(u, tol=TOL, mode=mode, restart=RESTART)
         ctx.energy_dev(None)
     torch.cuda.synchronize()
     infos, energies = [], []
     t0 = time.perf_counter()
     for _ in range(steps):
-        infos.append(ctx.solve_dev(u, tol=TOL, mode=mode))
+        infos.append(ctx.solve_dev(u, tol=TOL, mode=mode, restart=RESTART))
         energies.append(ctx.energy_dev(None))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -179,7 +180,7 @@ def run_solver(ctx, gabi, torch, u, mode, steps, warmup, event_solves, pairs):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(event_solves):
-        timed_infos.append(ctx.solve_dev(u, tol=TOL, mode=mode))
+        timed_infos.append(ctx.solve_dev(u, tol=TOL, mode=mode, restart=RESTART))
         ctx.energy_dev(None)
     torch.cuda.synchronize()
     elapsed_timed = time.perf_counter() - t1
@@ -279,7 +280,7 @@ def cpu_baseline(problem, seconds, fp64_products, small=None):
     each row is a full sum over all sources), built as the CPU-baseline plan
     says (-O3 -march=native, no contraction: bitwise the default build).
     solve: the oracle's time for one whole solve of the workload, extrapolated
-    as (products of an FP64 GMRES(10) solve at the bench tolerance) x (product
+    as (products of an FP64 GMRES(m) solve at the bench tolerance) x (product
     time) + the source-term and energy sums at the same pair rate; small: one
     measured oracle solve (rhs + GMRES + energy) of a smaller workload."""
     import numpy as np
@@ -311,7 +312,7 @@ def cpu_baseline(problem, seconds, fp64_products, small=None):
     t_solve = (fp64_products * pairs + src_pairs) / (rate * 1e9)
     out["solve"] = {"kind": "extrapolated", "seconds_per_solve": round(t_solve, 3),
                     "solves_per_s": round(1.0 / t_solve, 6), "products": fp64_products,
-                    "basis": "products of the GPU FP64 GMRES(10) solve at the bench tolerance "
+                    "basis": f"products of the GPU FP64 GMRES({RESTART}) solve at the bench tolerance "
                              "(the oracle's count agrees within one at the stored workloads) "
                              "x the measured product rate"}
     if small is not None:
@@ -319,7 +320,7 @@ def cpu_baseline(problem, seconds, fp64_products, small=None):
         els = oracle.mesh_elements(ps.V, ps.F)
         t0 = time.perf_counter()
         _, E, info = oracle.solve(els, ps.pos, ps.q, ps.eps1, ps.eps2, ps.kappa,
-                                  restart=10, tol=TOL, maxit=1000)
+                                  restart=RESTART, tol=TOL, maxit=1000)
         ts = time.perf_counter() - t0
         out["small_solve"] = {"workload": f"N={els.n}, Nc={len(ps.q)}", "kind": "measured",
                               "seconds_per_solve": round(ts, 3),
@@ -342,12 +343,12 @@ def warm_sequence(ctx, gabi, p, steps):
     runs = {}
     for key, previous in (("cold", 0), ("warm", 1)):
         ctx.set_charges(P[0], p.q)
-        ctx.solve(tol=TOL, mode=gabi.SOLVE_MIXED_IR)
+        ctx.solve(tol=TOL, mode=gabi.SOLVE_MIXED_IR, restart=RESTART)
         its, energies, seconds = [], [], 0.0
         for Pk in P[1:]:
             t0 = time.perf_counter()
             ctx.set_charges(Pk, p.q)
-            _, info = ctx.solve(tol=TOL, mode=gabi.SOLVE_MIXED_IR, x0_previous=previous)
+            _, info = ctx.solve(tol=TOL, mode=gabi.SOLVE_MIXED_IR, restart=RESTART, x0_previous=previous)
             energies.append(ctx.energy())
             seconds += time.perf_counter() - t0
             if not info["converged"]:
@@ -485,7 +486,7 @@ def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves, tree_ste
            "speedup_mixed_over_fp64": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3)}
     if tree:
         out["tree_ir_solver"] = {
-            "method": "FP64 iterative refinement around GMRES(10) cycles on the treecode "
+            "method": f"FP64 iterative refinement around GMRES({RESTART}) cycles on the treecode "
                       "product (theta 0.7, degree 5, leaves of 256, pair terms in FP32); "
                       "residuals are FP64 direct products",
             "solves_per_s": round(tree["solves_per_s"], 4),
@@ -579,7 +580,7 @@ def main():
         "data": "synthetic (seeded surface and charges)",
         "config": {"workload": head["workload"], "N": head["N"], "Nc": head["Nc"],
                    "eps1": p.eps1, "eps2": p.eps2, "kappa": p.kappa,
-                   "restart": 10, "tol": TOL, "solver": "mixed IR (FP32-pair GMRES "
+                   "restart": RESTART, "tol": TOL, "solver": "mixed IR (FP32-pair GMRES "
                    "cycles, FP64 residuals)", "parallelism": "single GPU"},
         "solves_per_s": mixed["solves_per_s"],
         "energy_rel_err": mixed["energy_rel_err"],

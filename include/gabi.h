@@ -82,7 +82,8 @@ typedef enum {
 } gabi_solve_mode;
 
 typedef struct {
-    int32_t restart;   /* m, Krylov steps per cycle, 1..64 (default 10)       */
+    int32_t restart;   /* m, Krylov steps per cycle, 1..64 (default 20, the
+                          top of the 10-20 of Section 2.4)                   */
     int32_t maxit;     /* cap on Arnoldi steps over the whole solve (100)     */
     double tol;        /* stop when ||b - A u|| / ||b|| <= tol (1e-6), with
                           the residual always formed with the FP64 product    */
@@ -90,7 +91,7 @@ typedef struct {
     double inner_tol;  /* MIXED_IR: each refinement step is one GMRES(m)
                           cycle on the FP32-pair product; it stops early once
                           its estimate falls below inner_tol times the
-                          current residual (1e-5)                             */
+                          current residual (3e-6)                             */
     int32_t max_outer; /* MIXED_IR: cap on refinement steps (20)              */
     int32_t use_graph; /* replay each round (cycle, update, residual) as a
                           captured HIP graph (1); with kernel timing on, the

@@ -361,11 +361,11 @@ extern "C" {
 
 void gabi_default_opts(gabi_solve_opts *o) {
     if (!o) return;
-    o->restart = 10;
+    o->restart = 20;
     o->maxit = 100;
     o->tol = 1e-6;
     o->mode = GABI_SOLVE_FP64;
-    o->inner_tol = 1e-5;
+    o->inner_tol = 3e-6;
     o->max_outer = 20;
     o->use_graph = 1;
     o->x0_previous = 0;

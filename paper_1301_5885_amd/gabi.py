@@ -601,7 +601,7 @@ class Context:
 # ---------------------------------------------------------------------------
 # many molecules
 # ---------------------------------------------------------------------------
-def solve_footprint(n, nc, restart=10):
+def solve_footprint(n, nc, restart=20):
     """Device bytes one solve holds (the unit of admission)."""
     return int(load().gabi_solve_footprint(int(n), int(nc), int(restart)))
 

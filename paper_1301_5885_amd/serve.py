@@ -4,7 +4,7 @@ The request mix: seeded star-shaped surfaces with N = 20 nu^2 log-uniform in
 [1280, 81920], Nc = N/40 charges, kappa ~ U[0, 0.3] (`synth.serving_requests`).
 Three ways of serving the same stream are measured:
 
-  plain FP64    one solve at a time through a context, restarted GMRES(10)
+  plain FP64    one solve at a time through a context, restarted GMRES(20)
                 on the FP64 product (the paper's solver, kept on the device);
   plain mixed   the same with FP64 iterative refinement around FP32-pair
                 GMRES cycles;

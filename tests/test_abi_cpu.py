@@ -44,7 +44,8 @@ def test_library_is_gfx950():
 
 def test_default_opts():
     o = gabi.default_opts()
-    assert (o.restart, o.maxit, o.tol, o.mode) == (10, 100, 1e-6, gabi.SOLVE_FP64)
+    assert (o.restart, o.maxit, o.tol, o.mode) == (20, 100, 1e-6, gabi.SOLVE_FP64)
+    assert o.inner_tol == 3e-6
 
 
 @pytest.mark.parametrize("kind", ["sphere", "star"])

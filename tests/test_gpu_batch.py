@@ -146,11 +146,12 @@ def test_graph_replay_matches_eager():
         ctx.set_surface_mesh(V, F)
         ctx.set_charges(pos, q)
         ctx.set_params(1.0, 80.0, 0.1257)
-        u_eager, i_eager = ctx.solve(tol=1e-10, use_graph=0)
+        # GMRES(10): several cycles, hence several replays, per solve
+        u_eager, i_eager = ctx.solve(tol=1e-10, use_graph=0, restart=10)
         v = rng.normal(size=2 * len(F))
         y0 = ctx.matvec(v)
         for _ in range(3):
-            u_graph, i_graph = ctx.solve(tol=1e-10, use_graph=1)
+            u_graph, i_graph = ctx.solve(tol=1e-10, use_graph=1, restart=10)
             assert i_graph["restarts"] >= 2          # several replays per solve
             assert np.array_equal(u_graph, u_eager)
             assert np.array_equal(ctx.matvec(v), y0)
@@ -163,12 +164,12 @@ def test_graph_replay_matches_eager():
         ctx.kernel_time(gabi.FP64, reset=True)
         ctx.set_kernel_timing(True)
         for _ in range(2):
-            u_timed, i_timed = ctx.solve(tol=1e-10, use_graph=1)
+            u_timed, i_timed = ctx.solve(tol=1e-10, use_graph=1, restart=10)
             assert np.array_equal(u_timed, u_eager)
         ctx.set_kernel_timing(False)
         ms, count = ctx.kernel_time(gabi.FP64, reset=True)
         assert ms > 0 and count >= 2 * i_timed["matvecs_fp64"] - 2
-        u_after, _ = ctx.solve(tol=1e-10, use_graph=1)   # captured again without events
+        u_after, _ = ctx.solve(tol=1e-10, use_graph=1, restart=10)   # recaptured, no events
         assert np.array_equal(u_after, u_eager)
 
 

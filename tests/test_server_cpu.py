@@ -47,7 +47,7 @@ def test_footprint_accounting():
 
 def test_tiny_budget_serialises_and_nothing_fails():
     reqs = [request(8, tag=i, seed=i) for i in range(6)]
-    fp = gabi.solve_footprint(reqs[0].n, reqs[0].nc, 10)
+    fp = gabi.solve_footprint(reqs[0].n, reqs[0].nc, gabi.default_opts().restart)
     with gabi.Server(device=-1, budget_bytes=int(1.5 * fp), max_slots=8,
                      mock_round_seconds=0.002) as s:
         res, st = run(s, reqs)
@@ -77,7 +77,8 @@ def test_slot_limit_and_overlap():
     assert overlap
     # results carry the footprint they held and sane timestamps
     for r in res:
-        assert r["device_bytes"] == gabi.solve_footprint(reqs[r["tag"]].n, reqs[r["tag"]].nc, 10)
+        assert r["device_bytes"] == gabi.solve_footprint(reqs[r["tag"]].n, reqs[r["tag"]].nc,
+                                                         gabi.default_opts().restart)
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
 
 
@@ -153,8 +154,9 @@ def test_round_cap_serves_the_oldest_first():
     def run_pair(slack):
         large = request(48, tag=0, seed=1)     # N = 46080: 12 mock rounds
         medium = request(24, tag=1, seed=2)    # N = 11520: 3 mock rounds
+        # maxit above the mock's 12 rounds of m steps
         with gabi.Server(device=-1, budget_bytes=1 << 34, max_slots=4,
-                         mock_round_seconds=0.01) as s:
+                         mock_round_seconds=0.01, maxit=1000) as s:
             if slack is not None:
                 s.set_round_cap(slack, 0)
             s.submit(large)
