@@ -29,9 +29,9 @@
 // (tree_wsum), the sums (tree_eval) and their reduction (tree_finish).  A batch's interaction
 // list is cut into work items of a bounded number of sources, one workgroup
 // each: the item's sources are staged through LDS 256 records at a time and
-// every target of the batch is served by 256/P threads (P the batch size
-// rounded up to a power of two) that take interleaved sources, their sums
-// added in thread order; the item writes one partial per target, and
+// every target of the batch is served by 256/P threads (P the batch size,
+// integer division) that take interleaved sources, their sums added in
+// thread order; the item writes one partial per target, and
 // tree_finish adds a batch's items in list order.  In the treecode
 // refinement (GABI_SOLVE_TREE_IR) the same kernels form the inner products of
 // a GMRES cycle: the finish then stores the sums in element order as the
@@ -391,10 +391,10 @@ __global__ __launch_bounds__(kBlock) void tree_wsum_kernel(TreeDev T, const Kryl
 
 // The sums of one work item: the batch's targets against the sources of its
 // list entries [l0, l1) in list order (near: elements, the target itself
-// skipped; far: proxies).  Thread t serves target t mod P with the sources
-// j = t / P (mod G) of every staged chunk, G = 256 / P; the G sums of a
-// target are added in thread order through LDS and stored as the item's
-// partial.  F32: the pair terms in FP32 (the direct product's pair_f32, on
+// skipped; far: proxies).  With P targets in the batch and G = 256 / P
+// (integer division), thread t < G P serves target t mod P with the sources
+// j = t / P (mod G) of every staged chunk; the G sums of a target are added
+// in thread order through LDS and stored as the item's partial.  F32: the pair terms in FP32 (the direct product's pair_f32, on
 // coordinates relative to the centre of the surface's bounding box), each
 // staged chunk summed in FP32 and added to FP64 sums.
 template <bool F32>
@@ -408,13 +408,11 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
     if (skip && load_done(st)) return;
     const int4 item = T.items[blockIdx.x];
     const int4 bt = T.batches[item.x];
-    const int bsz = bt.y - bt.x;
-    int P = 1;
-    while (P < bsz) P <<= 1;
+    const int P = bt.y - bt.x;  // 1 <= P <= kBlock targets
     const int G = kBlock / P;
     const int tid = (int)threadIdx.x, tg = tid % P, grp = tid / P;
     const int p = bt.x + tg;
-    const bool act = tg < bsz;
+    const bool act = grp < G;  // the last kBlock mod P threads idle
     const int pc_ = act ? p : bt.x;
     V4 x, nu;
     if constexpr (F32) {
@@ -445,6 +443,7 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
             }
             __syncthreads();
             const bool self = !far && j0 < bt.y && j0 + cnt > bt.x;
+            if (!act) continue;
             if constexpr (F32) {
                 float t32 = 0.0f, b32 = 0.0f;
                 for (int jj = grp; jj < cnt; jj += G) {
