@@ -28,10 +28,11 @@
 // clusters do not serialise the launch) and their sum in piece order
 // (tree_wsum), the sums (tree_eval) and their reduction (tree_finish).  A batch's interaction
 // list is cut into work items of a bounded number of sources, one workgroup
-// each: the item's sources are staged through LDS 256 records at a time and
-// every target of the batch is served by 256/P threads (P the batch size,
-// integer division) that take interleaved sources, their sums added in
-// thread order; the item writes one partial per target, and
+// each: the item's sources are staged through LDS up to 256 records at a
+// time, consecutive list entries packed into one stage (the entry holding
+// the batch's own elements is staged alone), and every target of the batch
+// is served by 256/P threads (P the batch size, integer division) that take
+// interleaved sources, their sums added in thread order; the item writes one partial per target, and
 // tree_finish adds a batch's items in list order.  In the treecode
 // refinement (GABI_SOLVE_TREE_IR) the same kernels form the inner products of
 // a GMRES cycle: the finish then stores the sums in element order as the
@@ -391,12 +392,14 @@ __global__ __launch_bounds__(kBlock) void tree_wsum_kernel(TreeDev T, const Kryl
 
 // The sums of one work item: the batch's targets against the sources of its
 // list entries [l0, l1) in list order (near: elements, the target itself
-// skipped; far: proxies).  With P targets in the batch and G = 256 / P
-// (integer division), thread t < G P serves target t mod P with the sources
-// j = t / P (mod G) of every staged chunk; the G sums of a target are added
-// in thread order through LDS and stored as the item's partial.  F32: the pair terms in FP32 (the direct product's pair_f32, on
-// coordinates relative to the centre of the surface's bounding box), each
-// staged chunk summed in FP32 and added to FP64 sums.
+// skipped; far: proxies), staged in list order up to kBlock at a time.
+// With P targets in the batch and G = 256 / P (integer division), thread
+// t < G P serves target t mod P with the staged sources j = t / P (mod G)
+// of every stage; the G sums of a target are added in thread order through
+// LDS and stored as the item's partial.  F32: the pair terms in FP32 (the
+// direct product's pair_f32, on coordinates relative to the centre of the
+// surface's bounding box), each stage summed in FP32 and added to FP64
+// sums.
 template <bool F32>
 __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF64 pc,
                                                           PairConstF32 pc32,
@@ -423,45 +426,72 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
         nu = T.snrm[pc_];
     }
     double top = 0.0, bot = 0.0;
-    for (int e = item.y; e < item.z; ++e) {
-        const int4 it = T.list[e];
-        const bool far = it.x == 1;
-        const V4 *src_p, *src_w;
-        if constexpr (F32) {
-            src_p = far ? T.ppos32 : T.spos32;
-            src_w = far ? T.pw32 : T.sw32;
-        } else {
-            src_p = far ? T.ppos : T.spos;
-            src_w = far ? T.pw : T.sw;
-        }
-        for (int j0 = it.y; j0 < it.z; j0 += kBlock) {
-            const int cnt = min(kBlock, it.z - j0);
-            __syncthreads();
-            if (tid < cnt) {
-                s_pos[tid] = src_p[j0 + tid];
-                s_w[tid] = src_w[j0 + tid];
-            }
-            __syncthreads();
-            const bool self = !far && j0 < bt.y && j0 + cnt > bt.x;
-            if (!act) continue;
+    int e = item.y, off = 0;  // the next source: offset off into entry e
+    while (e < item.z) {
+        // One stage: either the rest (up to kBlock elements) of the entry
+        // that holds the batch's own elements, staged alone so that each
+        // target can skip itself, or up to kBlock sources taken from
+        // consecutive other entries, near and far alike.
+        int fill = 0, self0 = -1;  // self0 >= 0: the own entry's first staged element
+        __syncthreads();
+        for (;;) {
+            const int4 it = T.list[e];
+            const bool far = it.x == 1;
+            const bool own = !far && it.y < bt.y && it.z > bt.x;
+            if (own && fill > 0) break;
+            const V4 *src_p, *src_w;
             if constexpr (F32) {
-                float t32 = 0.0f, b32 = 0.0f;
-                for (int jj = grp; jj < cnt; jj += G) {
-                    if (self && j0 + jj == p) continue;
-                    const float4 q = s_pos[jj], w = s_w[jj];
-                    pair_f32(pc32, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
-                             w.w, t32, b32);
-                }
-                top += (double)t32;
-                bot += (double)b32;
+                src_p = far ? T.ppos32 : T.spos32;
+                src_w = far ? T.pw32 : T.sw32;
             } else {
-                for (int jj = grp; jj < cnt; jj += G) {
-                    if (self && j0 + jj == p) continue;
+                src_p = far ? T.ppos : T.spos;
+                src_w = far ? T.pw : T.sw;
+            }
+            const int j0 = it.y + off;
+            const int take = min(kBlock - fill, it.z - j0);
+            if (tid < take) {
+                s_pos[fill + tid] = src_p[j0 + tid];
+                s_w[fill + tid] = src_w[j0 + tid];
+            }
+            if (own) self0 = j0;
+            fill += take;
+            off += take;
+            if (j0 + take == it.z) {
+                ++e;
+                off = 0;
+            }
+            if (own || fill == kBlock || e == item.z) break;
+        }
+        __syncthreads();
+        if (!act) continue;
+        // the staged element that is the thread's own target (none outside
+        // the own entry's stage, whose loop alone carries the test)
+        const int skip_jj = self0 >= 0 ? p - self0 : -1;
+        if constexpr (F32) {
+            float t32 = 0.0f, b32 = 0.0f;
+            auto run = [&](auto test) {
+                for (int jj = grp; jj < fill; jj += G) {
+                    if (test && jj == skip_jj) continue;
+                    const float4 q = s_pos[jj], w = s_w[jj];
+                    pair_f32(pc32, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y,
+                             w.z, w.w, t32, b32);
+                }
+            };
+            if (self0 >= 0) run(std::true_type{});
+            else run(std::false_type{});
+            top += (double)t32;
+            bot += (double)b32;
+        } else {
+            auto run = [&](auto test) {
+                for (int jj = grp; jj < fill; jj += G) {
+                    if (test && jj == skip_jj) continue;
                     const double4 q = s_pos[jj], w = s_w[jj];
                     pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
                              w.w, top, bot);
                 }
-            }
+            };
+            if (self0 >= 0) run(std::true_type{});
+            else run(std::false_type{});
         }
     }
     __syncthreads();
