@@ -23,9 +23,9 @@
 //    an inner node hands over to its children.
 //
 // Per product five kernels run: weights in tree order (tree_prep), the
-// modified weights of every proxy cluster in pieces of at most 2,048
-// elements (tree_weights, one workgroup per piece, so that the largest
-// clusters do not serialise the launch) and their sum in piece order
+// modified weights of every proxy cluster in pieces of 256-2,048 elements
+// (tree_weights, one workgroup per piece, so that the largest clusters do
+// not serialise the launch and small trees still fill the device) and their sum in piece order
 // (tree_wsum), the sums (tree_eval) and their reduction (tree_finish).  A batch's interaction
 // list is cut into work items of a bounded number of sources, one workgroup
 // each: the item's sources are staged through LDS up to 256 records at a
@@ -95,6 +95,7 @@ struct TreeState {
     int4 *pieces = nullptr;    // (cluster, element begin, element end, 0)
     double4 *wpart = nullptr;  // [piece][P] partial modified weights
     int n_pieces = 0;
+    int piece = 0;             // elements per piece (the last of a cluster: fewer)
     int64_t generation = 0;  // counts rebuilds (captured rounds compare it)
 };
 
@@ -277,7 +278,7 @@ struct TreeDev {
     const int4 *clusters, *batches, *list, *items, *pieces;
     double2 *ipart;
     double4 *wpart;
-    int n, degree, P;
+    int n, degree, P, piece;
     double bary[kTreeMaxDeg + 1];
 };
 
@@ -298,14 +299,16 @@ __global__ __launch_bounds__(kBlock) void tree_prep_kernel(TreeDev T, const doub
     if constexpr (F32) T.sw32[p] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)w.w);
 }
 
-// Partial modified weights of one piece (at most kTreePiece elements) of a
+// Partial modified weights of one piece (at most T.piece elements) of a
 // proxy cluster: W_k = sum_j L_k(y_j) w_j over the piece's elements in tree
 // order.  The 1-D bases of 64 elements are formed at a time (one (element,
 // dimension) per thread), then each thread adds the chunk's terms to its
 // proxies k = tid, tid + 256, ...
 constexpr int kTreeChunk = 64;
 constexpr int kTreeProxPerThread = (729 + kBlock - 1) / kBlock;
-constexpr int kTreePiece = 2048;  // elements per workgroup of the modified weights
+// elements per workgroup of the modified weights: the largest power of two
+// in [kTreePieceMin, kTreePieceMax] that still gives kTreePieceGroups pieces
+constexpr int kTreePieceMax = 2048, kTreePieceMin = 256, kTreePieceGroups = 1024;
 
 __global__ __launch_bounds__(kBlock) void tree_weights_kernel(TreeDev T, const KrylovStatus *st,
                                                              int skip) {
@@ -377,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void tree_wsum_kernel(TreeDev T, const Kryl
     const int4 cl = T.clusters[blockIdx.x];
     const int k = (int)(blockIdx.y * kBlock + threadIdx.x);
     if (k >= T.P) return;
-    const int count = (cl.y - cl.x + kTreePiece - 1) / kTreePiece;
+    const int count = (cl.y - cl.x + T.piece - 1) / T.piece;
     double4 a = T.wpart[(size_t)cl.w * T.P + k];
     for (int q = 1; q < count; ++q) {
         const double4 v = T.wpart[(size_t)(cl.w + q) * T.P + k];
@@ -622,13 +625,19 @@ int tree_ensure(gabi_ctx *ctx, const gabi_tree_opts *o) {
                 make_double4(cn[k1], cn[np1 + k2], cn[2 * np1 + k3], 0.0);
         }
     }
-    // pieces of at most kTreePiece elements per proxy cluster, in cluster
-    // order, so that large clusters spread over many workgroups
+    // pieces of at most T.piece elements per proxy cluster, in cluster
+    // order, so that large clusters spread over many workgroups; smaller
+    // pieces where the clusters hold few elements in all, so that the launch
+    // still has about kTreePieceGroups workgroups
+    int64_t members = 0;
+    for (int c = 0; c < nc; ++c) members += clusters[(size_t)c].y - clusters[(size_t)c].x;
+    T.piece = kTreePieceMax;
+    while (T.piece > kTreePieceMin && members / T.piece < kTreePieceGroups) T.piece /= 2;
     std::vector<int4> pieces;
     for (int c = 0; c < nc; ++c) {
         clusters[(size_t)c].w = (int)pieces.size();
-        for (int b0 = clusters[(size_t)c].x; b0 < clusters[(size_t)c].y; b0 += kTreePiece)
-            pieces.push_back(make_int4(c, b0, std::min(b0 + kTreePiece, clusters[(size_t)c].y), 0));
+        for (int b0 = clusters[(size_t)c].x; b0 < clusters[(size_t)c].y; b0 += T.piece)
+            pieces.push_back(make_int4(c, b0, std::min(b0 + T.piece, clusters[(size_t)c].y), 0));
     }
     T.n_pieces = (int)pieces.size();
     std::vector<float4> ppos32(ppos.size());
@@ -771,6 +780,7 @@ TreeDev tree_dev(const TreeState &T) {
     d.sw32 = T.sw32;
     d.pw32 = T.pw32;
     d.n = T.n;
+    d.piece = T.piece;
     d.degree = T.degree;
     d.P = T.P;
     for (int k = 0; k <= kTreeMaxDeg; ++k) d.bary[k] = T.bary[k];
