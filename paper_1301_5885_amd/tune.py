@@ -10,9 +10,10 @@ last round.  This module times the whole product (pair kernel plus the
 ordered split reduction) on geodesic spheres of one representative size per
 N bucket (bucket = floor(log2 N)), for both pair precisions: first every
 (R, target_blocks) without a tail, then the three fastest of those with
-each tail length, and the symmetric scheme (whose block pairs come in
-round-robin rounds; it has no shape parameter here: its passes follow from
-the partial-sum budget), and writes the fastest entry per bucket as JSON.  The
+each tail length (up to every split a 64-source piece), and the symmetric
+scheme (whose block pairs come in round-robin rounds; it has no shape
+parameter here: its passes follow from the partial-sum budget), and writes
+the fastest entry per bucket as JSON.  The
 library applies that table when it is loaded (`gabi.TUNING_PATH`).
 
 The decomposition fixes the order of the row sums, so a table change
@@ -112,10 +113,12 @@ def tune(buckets, reps, out_path):
                     rows.append((ms, gabi.SCHEME_SPLIT, R, tb, 0))
             rows.sort()
             untailed = rows[0]
+            # tails up to every source split a 64-source piece: at small N
+            # whole 256-source tiles leave most of the device idle
+            all_pieces = -(-n // 64)
+            tails = sorted({t for t in TAILS if t < all_pieces} | {all_pieces, -(-all_pieces // 2)})
             for _, _, R, tb, _ in rows[:3]:
-                for tail in TAILS:
-                    if tail * 64 >= n // 2:
-                        continue
+                for tail in tails:
                     gabi.tune_set(prec, b, gabi.SCHEME_SPLIT, R, tb, tail)
                     ms = time_product(V, F, prec, reps)
                     rows.append((ms, gabi.SCHEME_SPLIT, R, tb, tail))
