@@ -18,9 +18,11 @@
 // the device) and zero counters into the scratch, so nothing carries over
 // between calls.  The number of partial-sum slots per pass is the most that
 // fit beside the fixed parts; a product needs more passes than the context's
-// (whose slots follow the partial-sum budget) when N is large, so the two
-// entry points may add the same terms in a different slot grouping: equal up
-// to rounding, not bit for bit.  Calls on one device share its scratch and
+// (whose slots follow the partial-sum budget) when N is large, and the
+// context takes the tuned decomposition (the split scheme at small N), so
+// the two entry points may add the same terms in a different grouping:
+// equal up to rounding, bit for bit only where both take the symmetric
+// scheme in the same passes.  Calls on one device share its scratch and
 // must not overlap (one stream, or synchronised streams).
 #include <mutex>
 

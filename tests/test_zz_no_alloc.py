@@ -6,8 +6,9 @@ Two calls in a row, the second on a smaller surface, so the second reuses
 (and must fully rewrite) the scratch the first left behind: the first is
 large enough that the allocation-free product takes several passes while
 the context takes one (equal to rounding, within the FP64 parity bound
-1e-10 of the other product tests); the second takes one pass in both and
-is bitwise equal.  Sizes beyond the scratch are rejected with an error.
+1e-10 of the other product tests); the second takes the symmetric scheme
+in one pass in both (the context's tuned scheme from N = 8,192 on) and is
+bitwise equal.  Sizes beyond the scratch are rejected with an error.
 """
 import sys
 
@@ -51,8 +52,10 @@ def test_noalloc_product_matches_context_product():
     nc = gabi.Context(0)
     nc.set_params(EPS1, EPS2, KAPPA)
     try:
-        # nu = 50: N = 50,000 (196 blocks, ragged); nu = 17: N = 5,780 (23 blocks)
-        for k, (nu, R) in enumerate(((50, 32.0), (17, 11.0))):
+        # nu = 50: N = 50,000 (196 blocks, ragged); nu = 21: N = 8,820 (35
+        # blocks, ragged), where the context's tuned decomposition is the
+        # symmetric scheme in one pass, as the allocation-free product's
+        for k, (nu, R) in enumerate(((50, 32.0), (21, 13.0))):
             V, F = icosphere(nu, R)
             n = len(F)
             log(f"[noalloc] call {k + 1}: N={n}")
