@@ -426,14 +426,18 @@ def tree_crossover(gabi, torch, nus=(16, 32, 40, 48, 56, 64, 96, 128), reps=3):
             f"ms, err {err:.2e} (fp32 evaluation {t_tree32:.3f} ms, err {err32:.2e})")
     faster = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp64_ms"]]
     faster32 = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp32_pair_ms"]]
+    faster3232 = [r["N"] for r in rows if r["tree_fp32_ms"] < r["direct_fp32_pair_ms"]]
     return {"opts": {"theta": theta, "degree": degree, "leaf_size": leaf},
-            "method": "barycentric Lagrange treecode (particle-cluster, target batches), FP64",
+            "method": "barycentric Lagrange treecode (particle-cluster, target batches), FP64 "
+                      "sums, and FP32 sums (tree_fp32_*)",
             "rows": rows,
             "crossover_N_vs_fp64": faster[0] if faster else None,
             "crossover_N_vs_fp32_pair": faster32[0] if faster32 else None,
-            "crossover_note": "smallest measured N with the treecode product faster than "
-                              "the direct FP64 (FP32-pair) product (None: not within the sizes "
-                              "measured)"}
+            "crossover_N_fp32_sums_vs_fp32_pair": faster3232[0] if faster3232 else None,
+            "crossover_note": "smallest measured N with the treecode product (FP64 sums) faster "
+                              "than the direct FP64 (FP32-pair) product, and with FP32 sums "
+                              "faster than the direct FP32-pair product (None: not within the "
+                              "sizes measured)"}
 
 
 def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves, tree_steps=0):
