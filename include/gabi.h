@@ -209,8 +209,9 @@ int gabi_matvec_dev(gabi_ctx *ctx, int precision, const double *u_dev,
  * Errors: GABI_ESTATE (no parameters), GABI_EINVAL (size, null or
  * misaligned pointer), GABI_EDEVICE.  Results equal gabi_matvec_dev's at
  * GABI_FP64 up to the grouping of partial sums: bit for bit where the
- * context takes the symmetric scheme in one pass (n <= 20,480 with the
- * shipped tuning table and the default partial-sum budget).               */
+ * context takes the symmetric scheme in one pass (8,192 <= n <= 20,480 with
+ * the shipped tuning table and the default partial-sum budget; below 8,192
+ * the table picks the split scheme).                                       */
 int gabi_matvec_noalloc(gabi_ctx *ctx, int64_t n, const double *elem_dev,
                         const double *u_dev, double *y_dev);
 
