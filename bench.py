@@ -529,7 +529,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-caps", default=None,
                     help="round caps of the served runs (serve.py --caps; default: "
-                         "slack 0.25 and floor 32768, then none)")
+                         "slack 0.5 and floor 32768, then none)")
     ap.add_argument("--sequence-steps", type=int, default=8,
                     help="nearby problems solved cold and warm-started after the timing, "
                          "on the secondary workload (0: skip)")

@@ -41,9 +41,9 @@ import numpy as np
 TOL = 1e-8
 ARRIVAL_SEED = 6000
 LOAD = 0.8
-# served runs: under the round cap slack 0.25, floor 32,768 elements (the
+# served runs: under the round cap slack 0.5, floor 32,768 elements (the
 # reported figures), then without a cap for comparison
-DEFAULT_CAPS = "0.25:32768,none"
+DEFAULT_CAPS = "0.5:32768,none"
 
 
 def log(*a):
