@@ -88,11 +88,12 @@ typedef struct {
     double tol;        /* stop when ||b - A u|| / ||b|| <= tol (1e-6), with
                           the residual always formed with the FP64 product    */
     int32_t mode;      /* gabi_solve_mode (GABI_SOLVE_FP64)                   */
-    double inner_tol;  /* MIXED_IR: each refinement step is one GMRES(m)
-                          cycle on the FP32-pair product; it stops early once
-                          its estimate falls below inner_tol times the
-                          current residual (3e-6)                             */
-    int32_t max_outer; /* MIXED_IR: cap on refinement steps (20)              */
+    double inner_tol;  /* MIXED_IR, TREE_IR: each refinement step is one
+                          GMRES(m) cycle on the FP32-pair (treecode) product;
+                          it stops early once its estimate falls below
+                          max(inner_tol, 0.1 tol ||b|| / ||r||) times the
+                          current residual r (inner_tol 3e-6)                 */
+    int32_t max_outer; /* MIXED_IR, TREE_IR: cap on refinement steps (20)     */
     int32_t use_graph; /* replay each round (cycle, update, residual) as a
                           captured HIP graph (1); with kernel timing on, the
                           captured round records events around its products */
