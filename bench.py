@@ -417,17 +417,28 @@ def tree_crossover(gabi, torch, nus=(16, 32, 40, 48, 56, 64, 96, 128), reps=3):
             ctx.tree_matvec_dev(u, yt, theta, degree, leaf, gabi.FP32_PAIR)
             torch.cuda.synchronize()
             err32 = float(torch.linalg.norm(yt - y) / torch.linalg.norm(y))
+        tree_pairs = info["far_pairs"] + info["near_pairs"]
         rows.append({"N": n, "direct_fp64_ms": round(t64, 4), "direct_fp32_pair_ms": round(t32, 4),
                      "tree_fp64_ms": round(t_tree, 4), "tree_rel_err_vs_direct": err,
                      "tree_fp32_ms": round(t_tree32, 4), "tree_fp32_rel_err_vs_direct": err32,
-                     "tree_pairs_per_product": info["far_pairs"] + info["near_pairs"],
+                     "tree_pairs_per_product": tree_pairs,
+                     "tree_fp64_tflops": round(tree_pairs * FLOP_PER_PAIR / t_tree / 1e9, 2),
+                     "tree_fp32_tflops": round(tree_pairs * FLOP_PER_PAIR / t_tree32 / 1e9, 2),
                      "tree_device_bytes": info["device_bytes"]})
         log(f"[bench] tree N={n}: direct {t64:.3f} ms (fp32-pair {t32:.3f}), tree {t_tree:.3f} "
             f"ms, err {err:.2e} (fp32 evaluation {t_tree32:.3f} ms, err {err32:.2e})")
     faster = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp64_ms"]]
     faster32 = [r["N"] for r in rows if r["tree_fp64_ms"] < r["direct_fp32_pair_ms"]]
     faster3232 = [r["N"] for r in rows if r["tree_fp32_ms"] < r["direct_fp32_pair_ms"]]
+    big = rows[-1]
     return {"opts": {"theta": theta, "degree": degree, "leaf_size": leaf},
+            "roofline": {"bound": "alu", "achieved": big["tree_fp32_tflops"],
+                         "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                         "frac": round(big["tree_fp32_tflops"] / PEAK_TFLOPS["fp32"], 4),
+                         "N": big["N"],
+                         "basis": "treecode product with FP32 sums: 61 algorithmic FLOP per "
+                                  "evaluated pair (near element pairs and proxy pairs) over the "
+                                  "product's device time (all its kernels)"},
             "method": "barycentric Lagrange treecode (particle-cluster, target batches), FP64 "
                       "sums, and FP32 sums (tree_fp32_*)",
             "rows": rows,
