@@ -500,10 +500,11 @@ def measure(gabi, torch, name, steps, warmup, fp64_steps, event_solves, tree_ste
            "mixed": solver_line(mixed, "fp32"), "fp64_solver": solver_line(fp64, "fp64"),
            "speedup_mixed_over_fp64": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3)}
     if tree:
+        dflt = gabi.default_opts()
         out["tree_ir_solver"] = {
             "method": f"FP64 iterative refinement around GMRES({RESTART}) cycles on the treecode "
-                      "product (theta 0.7, degree 5, leaves of 256, pair terms in FP32); "
-                      "residuals are FP64 direct products",
+                      f"product (theta {dflt.tree_theta:g}, degree {dflt.tree_degree}, leaves of "
+                      f"{dflt.tree_leaf}, pair terms in FP32); residuals are FP64 direct products",
             "solves_per_s": round(tree["solves_per_s"], 4),
             "ms_per_step": round(tree["ms_per_step"], 4), "steps": tree["steps"],
             "energy": tree["energy"], "energy_rel_err": tree["energy_rel_err"],

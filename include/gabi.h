@@ -106,7 +106,7 @@ typedef struct {
                           Section 4); 0, or no such solution, starts from
                           zero.  Batch and server calls ignore it (0)         */
     double tree_theta;   /* TREE_IR: treecode options of the inner products  */
-    int32_t tree_degree; /* (gabi_tree_opts; defaults 0.7, 5, 256 and         */
+    int32_t tree_degree; /* (gabi_tree_opts; defaults 0.6, 4, 128 and         */
     int32_t tree_leaf;   /* GABI_FP32_PAIR: the residuals are FP64 direct      */
     int32_t tree_precision; /* products whatever the inner precision)        */
 } gabi_solve_opts;
