@@ -127,14 +127,27 @@ def fp32_tol(el):
     return max(2e-6, 2.0 ** -24 * L / h)
 
 
-@pytest.mark.parametrize("name", ["large_327680", "star_81920"])
+def sampled_problem(name):
+    if name.startswith("sphere"):
+        nu = {"sphere_23120": 34, "sphere_32000": 40}[name]
+        V, F = icosphere(nu, math.sqrt(20 * nu * nu / (16 * math.pi)))
+        pos = charges_in_ball(np.random.default_rng(nu), 50, 0.8 * math.sqrt(20 * nu * nu / (16 * math.pi)))
+        return V, F, pos, np.random.default_rng(nu + 1).normal(0.0, 0.5, 50)
+    p = config_problem("large" if name.startswith("large") else "star")
+    return p.V, p.F, p.pos, p.q
+
+
+@pytest.mark.parametrize("name", ["large_327680", "star_81920", "sphere_32000", "sphere_23120"])
 @pytest.mark.parametrize("precision", [gabi.FP64, gabi.FP32_PAIR])
 def test_matvec_full_size_sampled_rows(ctx, name, precision):
-    """Full-size workloads in the benchmark's launch configuration; the
-    oracle evaluates 768 sampled rows of the product."""
-    p = config_problem("large" if name.startswith("large") else "star")
-    log(f"[matvec sampled] {name} N={p.n} precision={precision}")
-    el = load(ctx, p.V, p.F, p.pos, p.q)
+    """Full-size workloads in the benchmark's launch configuration, and two
+    spheres whose FP32-pair tile lists are short enough to be taken by local
+    index (N = 23,120 and 32,000: up to three and four tiles per workgroup;
+    their FP64 lists, of half as many workgroups, go through the counters);
+    the oracle evaluates 768 sampled rows of the product."""
+    V, F, pos, q = sampled_problem(name)
+    log(f"[matvec sampled] {name} N={len(F)} precision={precision}")
+    el = load(ctx, V, F, pos, q)
     rng = np.random.default_rng(99)
     u = rng.normal(size=2 * el.n)
     y = ctx.matvec(u, precision)
