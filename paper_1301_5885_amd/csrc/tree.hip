@@ -31,8 +31,9 @@
 // each: the item's sources are staged through LDS up to 256 records at a
 // time, consecutive list entries packed into one stage (the entry holding
 // the batch's own elements is staged alone), and every target of the batch
-// is served by 256/P threads (P the batch size, integer division) that take
-// interleaved sources, their sums added in thread order; the item writes one partial per target, and
+// is served by 256/H threads (H half the batch size, rounded up; integer
+// division), each thread serving two targets, that take interleaved
+// sources, their sums added in thread order; the item writes one partial per target, and
 // tree_finish adds a batch's items in list order.  In the treecode
 // refinement (GABI_SOLVE_TREE_IR) the same kernels form the inner products of
 // a GMRES cycle: the finish then stores the sums in element order as the
@@ -396,13 +397,15 @@ __global__ __launch_bounds__(kBlock) void tree_wsum_kernel(TreeDev T, const Kryl
 // The sums of one work item: the batch's targets against the sources of its
 // list entries [l0, l1) in list order (near: elements, the target itself
 // skipped; far: proxies), staged in list order up to kBlock at a time.
-// With P targets in the batch and G = 256 / P (integer division), thread
-// t < G P serves target t mod P with the staged sources j = t / P (mod G)
-// of every stage; the G sums of a target are added in thread order through
-// LDS and stored as the item's partial.  F32: the pair terms in FP32 (the
-// direct product's pair_f32, on coordinates relative to the centre of the
-// surface's bounding box), each stage summed in FP32 and added to FP64
-// sums.
+// Each thread serves two targets, t and t + H of the batch's P (H = the
+// half of P rounded up; the second is absent when t + H = P), so that a
+// staged source is read once for two pair terms.  With G = 256 / H
+// (integer division), thread t < G H serves targets t mod H and
+// t mod H + H with the staged sources j = t / H (mod G) of every stage; a
+// target's G sums are added in thread order through LDS and stored as the
+// item's partial.  F32: the pair terms in FP32 (the direct product's
+// pair_f32, on coordinates relative to the centre of the surface's bounding
+// box), each stage summed in FP32 and added to FP64 sums.
 template <bool F32>
 __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF64 pc,
                                                           PairConstF32 pc32,
@@ -410,25 +413,31 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
     using V4 = typename std::conditional<F32, float4, double4>::type;
     __shared__ V4 s_pos[kBlock];
     __shared__ V4 s_w[kBlock];
-    __shared__ double2 s_sum[kBlock];
+    __shared__ double2 s_sum[2][kBlock];
     if (skip && load_done(st)) return;
     const int4 item = T.items[blockIdx.x];
     const int4 bt = T.batches[item.x];
     const int P = bt.y - bt.x;  // 1 <= P <= kBlock targets
-    const int G = kBlock / P;
-    const int tid = (int)threadIdx.x, tg = tid % P, grp = tid / P;
-    const int p = bt.x + tg;
-    const bool act = grp < G;  // the last kBlock mod P threads idle
-    const int pc_ = act ? p : bt.x;
-    V4 x, nu;
+    const int H = (P + 1) / 2;
+    const int G = kBlock / H;
+    const int tid = (int)threadIdx.x, tg = tid % H, grp = tid / H;
+    const bool act = grp < G;           // the last kBlock mod H threads idle
+    const bool two = tg + H < P;        // the thread's second target exists
+    const int pa = bt.x + tg;
+    const int pb = two ? pa + H : pa;   // (absent: a copy of the first, discarded)
+    V4 xa, na, xb, nb;
     if constexpr (F32) {
-        x = T.spos32[pc_];
-        nu = T.snrm32[pc_];
+        xa = T.spos32[pa];
+        na = T.snrm32[pa];
+        xb = T.spos32[pb];
+        nb = T.snrm32[pb];
     } else {
-        x = T.spos[pc_];
-        nu = T.snrm[pc_];
+        xa = T.spos[pa];
+        na = T.snrm[pa];
+        xb = T.spos[pb];
+        nb = T.snrm[pb];
     }
-    double top = 0.0, bot = 0.0;
+    double topa = 0.0, bota = 0.0, topb = 0.0, botb = 0.0;
     int e = item.y, off = 0;  // the next source: offset off into entry e
     while (e < item.z) {
         // One stage: either the rest (up to kBlock elements) of the entry
@@ -467,30 +476,39 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
         }
         __syncthreads();
         if (!act) continue;
-        // the staged element that is the thread's own target (none outside
-        // the own entry's stage, whose loop alone carries the test)
-        const int skip_jj = self0 >= 0 ? p - self0 : -1;
+        // the staged elements that are the thread's own targets (none
+        // outside the own entry's stage, whose loop alone carries the test)
+        const int skip_a = self0 >= 0 ? pa - self0 : -1;
+        const int skip_b = self0 >= 0 ? pb - self0 : -1;
         if constexpr (F32) {
-            float t32 = 0.0f, b32 = 0.0f;
+            float ta = 0.0f, ba = 0.0f, tb = 0.0f, bb = 0.0f;
             auto run = [&](auto test) {
                 for (int jj = grp; jj < fill; jj += G) {
-                    if (test && jj == skip_jj) continue;
                     const float4 q = s_pos[jj], w = s_w[jj];
-                    pair_f32(pc32, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y,
-                             w.z, w.w, t32, b32);
+                    if (!(test && jj == skip_a))
+                        pair_f32(pc32, xa.x, xa.y, xa.z, na.x, na.y, na.z, q.x, q.y, q.z, w.x,
+                                 w.y, w.z, w.w, ta, ba);
+                    if (!(test && jj == skip_b))
+                        pair_f32(pc32, xb.x, xb.y, xb.z, nb.x, nb.y, nb.z, q.x, q.y, q.z, w.x,
+                                 w.y, w.z, w.w, tb, bb);
                 }
             };
             if (self0 >= 0) run(std::true_type{});
             else run(std::false_type{});
-            top += (double)t32;
-            bot += (double)b32;
+            topa += (double)ta;
+            bota += (double)ba;
+            topb += (double)tb;
+            botb += (double)bb;
         } else {
             auto run = [&](auto test) {
                 for (int jj = grp; jj < fill; jj += G) {
-                    if (test && jj == skip_jj) continue;
                     const double4 q = s_pos[jj], w = s_w[jj];
-                    pair_f64(pc, x.x, x.y, x.z, nu.x, nu.y, nu.z, q.x, q.y, q.z, w.x, w.y, w.z,
-                             w.w, top, bot);
+                    if (!(test && jj == skip_a))
+                        pair_f64(pc, xa.x, xa.y, xa.z, na.x, na.y, na.z, q.x, q.y, q.z, w.x, w.y,
+                                 w.z, w.w, topa, bota);
+                    if (!(test && jj == skip_b))
+                        pair_f64(pc, xb.x, xb.y, xb.z, nb.x, nb.y, nb.z, q.x, q.y, q.z, w.x, w.y,
+                                 w.z, w.w, topb, botb);
                 }
             };
             if (self0 >= 0) run(std::true_type{});
@@ -498,16 +516,19 @@ __global__ __launch_bounds__(kBlock) void tree_eval_kernel(TreeDev T, PairConstF
         }
     }
     __syncthreads();
-    s_sum[tid] = make_double2(top, bot);
+    s_sum[0][tid] = make_double2(topa, bota);
+    s_sum[1][tid] = make_double2(topb, botb);
     __syncthreads();
     if (grp == 0) {
-        double2 acc = s_sum[tg];
-        for (int g = 1; g < G; ++g) {
-            const double2 v = s_sum[g * P + tg];
-            acc.x += v.x;
-            acc.y += v.y;
+        for (int h = 0; h < (two ? 2 : 1); ++h) {
+            double2 acc = s_sum[h][tg];
+            for (int g = 1; g < G; ++g) {
+                const double2 v = s_sum[h][g * H + tg];
+                acc.x += v.x;
+                acc.y += v.y;
+            }
+            T.ipart[(size_t)blockIdx.x * kBlock + tg + h * H] = acc;
         }
-        T.ipart[(size_t)blockIdx.x * kBlock + tg] = acc;
     }
 }
 
